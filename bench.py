@@ -1,0 +1,182 @@
+#!/usr/bin/env python3
+"""Throughput of the sDEM total viewshed on one MI355X.
+
+One step = one tvs_total_viewshed call (all sectors: relocation, sweep, back-projection)
+on a device-resident synthetic DEM shaped like the paper's 2000x2000, 10 m workload.
+Prints one JSON line: LoS cell-evaluations/s (whole job), total-viewshed cells/s, the
+sweep kernel against its ALU roofline (kernel durations from HIP events recorded by the
+library on the call's stream inside the timed region) and the CPU oracle's rate on a
+bounded sample of the same workload.
+
+    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload tvs2000] [--flags 0]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs x 4 SIMD16 = 64 FP32 lanes per CU per clock, 2.4 GHz peak engine clock,
+# non-packed VALU issue (packed FP32 is not used). One line-of-sight evaluation is 5 algorithmic
+# operations: subtract, divide, compare, max, conditional integer add.
+CU, LANES, CLOCK_HZ = 256, 64, 2.4e9
+ALU_PEAK_OPS = CU * LANES * CLOCK_HZ          # 3.93e13 lane-ops/s
+OPS_PER_EVAL = 5
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="tvs2000")
+    ap.add_argument("--flags", type=int, default=0, help="TVS_FLAG_* bits (0 = default float path)")
+    ap.add_argument("--cpu-window", type=int, default=128, help="side of the centre window the oracle times")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.json"))
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        log("bench.py measures one GPU only: this build has no multi-GPU path "
+            "(sectors would shard across GPUs with one final reduce; see the design notes). Run with --gpus 1.")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2003_02200_amd as tvs
+    from synth import WORKLOADS, workload_dem
+
+    w = WORKLOADS[args.workload]
+    dem = workload_dem(args.workload)
+    H, W = dem.shape
+    call = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    evals, pairs = tvs.los_evals(H, W, *[call[0], call[2], call[3]])
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(dem).cuda()
+    torch.cuda.synchronize()
+    log(f"workload {args.workload}: {H}x{W}, {w['n_sectors']} sectors, {evals:.3e} LoS evals/step")
+
+    for i in range(args.warmup):
+        out = tvs.total_viewshed(d, *call, flags=args.flags)
+        torch.cuda.synchronize()
+        log(f"warmup {i} done")
+
+    sweep_ms = reloc_ms = back_ms = 0.0
+    sweep_n = reloc_n = back_n = 0
+    reloc_bytes = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out, st = tvs.total_viewshed(d, *call, flags=args.flags, stats=True)
+        sweep_ms += st.sweep_ms
+        reloc_ms += st.reloc_ms
+        back_ms += st.backproj_ms
+        sweep_n += st.sweep_launches
+        reloc_n += st.reloc_launches
+        back_n += st.backproj_launches
+        reloc_bytes += st.reloc_bytes
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    step_s = elapsed / args.steps
+    log(f"timed {args.steps} steps: {step_s * 1e3:.2f} ms/step")
+    res = out.cpu().numpy()
+    if not np.all(np.isfinite(res)):
+        log("non-finite output")
+        sys.exit(1)
+
+    # dominant kernel: the sweep (ALU bound)
+    avg_sweep_s = sweep_ms / 1e3 / max(sweep_n, 1)
+    ops_per_launch = OPS_PER_EVAL * evals * args.steps / max(sweep_n, 1)
+    achieved = ops_per_launch / avg_sweep_s if sweep_n else None
+    traffic = None
+    if os.path.exists(args.traffic_json):
+        try:
+            tj = json.load(open(args.traffic_json))
+            if tj.get("flags", 0) == args.flags and tj.get("workload") == args.workload:
+                traffic = tj.get("bytes_per_launch")
+        except (OSError, ValueError):
+            traffic = None
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12 if achieved else None,
+        "peak": ALU_PEAK_OPS / 1e12,
+        "unit": "TFLOP/s",
+        "frac": (achieved / ALU_PEAK_OPS) if achieved else None,
+        "traffic": traffic,
+        "kernel": "k_sweep",
+        "ops_per_eval": OPS_PER_EVAL,
+        "avg_launch_ms": avg_sweep_s * 1e3,
+        "launches": sweep_n,
+    }
+    kernels = {
+        "sweep_ms_per_step": sweep_ms / args.steps,
+        "relocate_ms_per_step": reloc_ms / args.steps,
+        "backproj_ms_per_step": back_ms / args.steps,
+        "relocate_alg_GBps": (reloc_bytes / (reloc_ms / 1e3) / 1e9) if reloc_ms > 0 else None,
+        "relocate_frac_hbm": ((reloc_bytes / (reloc_ms / 1e3) / 1e9) / HBM_PEAK_GBS) if reloc_ms > 0 else None,
+        "evals_per_s_sweep_only": evals * args.steps / (sweep_ms / 1e3) if sweep_ms > 0 else None,
+    }
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        cw = min(args.cpu_window, H, W)
+        r0, c0 = (H - cw) // 2, (W - cw) // 2
+        log(f"cpu baseline: oracle on a {cw}x{cw} centre window ...")
+        t1 = time.perf_counter()
+        _, ev_cpu = oracle.total(dem, *call, prec=64, window=(r0, c0, cw, cw), count=True)
+        cpu_s = time.perf_counter() - t1
+        cpu = {
+            "value": ev_cpu / cpu_s,
+            "unit": "LoS cell-evals/s",
+            "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": f"{cw}x{cw} centre cells of the {H}x{W} workload, all {w['n_sectors']} sectors, double "
+                      f"oracle (walks both skewed samples of every cell and sector): {ev_cpu:.3e} evals in "
+                      f"{cpu_s:.1f} s",
+            "cells_per_s": cw * cw / cpu_s,
+        }
+        log(f"cpu baseline: {ev_cpu / cpu_s:.3e} evals/s on {oracle.threads()} threads")
+
+    line = {
+        "metric": "LoS cell-evals/s + total-viewshed cells/s at 2000² DEM; p50/p99 serve latency",
+        "value": evals * args.steps / elapsed,
+        "unit": "LoS cell-evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.flags & tvs.FLAG_SLOPE_F64 else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.workload}: {H}x{W} diamond-square DEM (seed {w['seed']}, roughness {w['roughness']}, "
+                        f"0-{w['zmax']:.0f} m), spacing {w['spacing']} m, observer {w['obs_height']} m, "
+                        f"{w['n_sectors']} sectors, max distance {w['max_dist']:.0f} m",
+            "rows": H, "cols": W, "n_sectors": w["n_sectors"], "max_dist_m": w["max_dist"],
+            "flags": args.flags, "los_evals_per_step": evals, "pov_sector_pairs_per_step": pairs,
+        },
+        "total_viewshed_cells_per_s": H * W / step_s,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

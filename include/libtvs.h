@@ -1,0 +1,152 @@
+/*
+ * libtvs.h -- C ABI of libtvs, the MI355X (gfx950) implementation of the sDEM total
+ * viewshed (Sanchez-Fernandez, Romero, Bandera, Tabik, "A data relocation approach for
+ * terrain surface analysis on multi-GPU systems: a case study on the total viewshed
+ * problem").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * dem        Row-major, C-contiguous rows x cols float32 elevations in metres. Row index
+ *            grows "south", column index "east". Cells are square, `spacing` metres apart.
+ *            Every elevation must be finite (the paper has no no-data concept).
+ * spacing    Grid step in metres, finite and > 0.
+ * obs_height Height of the observer above the ground at the point of view (POV), metres,
+ *            finite. Targets are at ground level.
+ * n_sectors  Number of sector axes over 180 degrees, 1 <= n <= 32768. Axis k points at
+ *            a_k = k*pi/n from +column toward +row; each axis carries a forward and a
+ *            backward line of sight (a_k and a_k + 180 deg), each the axis of a
+ *            half-sector of opening pi/n (Section 3.1, Alg. 1; Section 4.1 step 1). The
+ *            paper's "ns sectors" is 2n.
+ * max_dist   Largest distance (metres) of a target from the POV: > 0, may be +INFINITY
+ *            (the paper's own unbounded setting). A line of sight of sector s' stops at
+ *            index distance m < rho = max_dist cos(s') / spacing and its last ring is
+ *            clipped at rho.
+ * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE.
+ * Results    Areas in square metres, double.
+ *
+ * Errors: every call returns TVS_OK (0) or a negative status; on error the outputs are
+ * left untouched, except the _async variants after device work was enqueued (then the
+ * status is TVS_EDEVICE). tvs_last_error() describes the last failure on the calling
+ * thread. No exception crosses the ABI. Every entry point is reentrant.
+ *
+ * Ownership: the caller owns every buffer. Host-pointer variants are synchronous and
+ * keep no pointer after return. _async variants take device pointers on the current
+ * HIP device and a hipStream_t (passed as void*, NULL = the null stream); they enqueue
+ * work on that stream and return; inputs must stay valid and outputs untouched until
+ * the stream reaches that point. Device scratch is allocated stream-ordered per call.
+ */
+#ifndef LIBTVS_H
+#define LIBTVS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TVS_ABI_VERSION 1
+
+enum tvs_status {
+    TVS_OK = 0,
+    TVS_EINVAL = -1,  /* bad argument: null pointer, size, non-finite value, POV outside the grid */
+    TVS_ENOMEM = -2,  /* host or device allocation failed */
+    TVS_EDEVICE = -3, /* a HIP call or kernel launch failed (see tvs_last_error) */
+    TVS_ERANGE = -4   /* grid side above 32767 */
+};
+
+/* Variant flags (the default, 0, is: float slopes with exactly rounded division, one
+ * lane per POV in the sweep, double per-cell accumulation). */
+#define TVS_FLAG_SLOPE_F64 0x1u   /* visibility decided in double from double elevations */
+#define TVS_FLAG_SWEEP_SCAN 0x2u  /* sweep with one lane per target and wavefront prefix-max */
+#define TVS_FLAG_ACC_KAHAN32 0x4u /* float Kahan-compensated per-cell accumulation */
+
+/* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
+ * times come from HIP events recorded around each launch on the call's stream; asking for
+ * them makes the call wait for its own work before returning. */
+typedef struct tvs_stats {
+    double reloc_ms;        /* summed duration of the relocation launches */
+    double sweep_ms;        /* summed duration of the sweep launches */
+    double backproj_ms;     /* summed duration of the back-projection launches */
+    int32_t reloc_launches;
+    int32_t sweep_launches;
+    int32_t backproj_launches;
+    int32_t chunks;         /* sector groups processed one after another */
+    int64_t los_evals;      /* line-of-sight cell evaluations of the call (closed form) */
+    int64_t pov_sector_pairs; /* skewed samples summed over sectors (one per POV and sector) */
+    int64_t reloc_bytes;    /* algorithmic bytes of the relocation: 4 read + element size written per sample */
+    int64_t sweep_bytes;    /* algorithmic bytes of the sweep: element size read + 4 written per sample */
+    int64_t scratch_bytes;  /* device scratch used */
+} tvs_stats;
+
+/* ABI version of the loaded library (TVS_ABI_VERSION of the build). */
+int tvs_abi_version(void);
+
+/* Text of the last error on the calling thread; valid until the next libtvs call on it. */
+const char *tvs_last_error(void);
+
+/* Total viewshed, Alg. 4 computed with the sDEM method of Section 4.1 (steps 1a-1d) and the
+ * three kernels of Section 4.2 (relocation Alg. 6, sweep Alg. 7/8, back-projection Alg. 9):
+ * out[i*cols + j] = area visible from cell (i, j), m^2. `dem` and `out` are host pointers
+ * (rows*cols each). Synchronous; runs on the current HIP device. */
+int tvs_total_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing,
+                       double obs_height, int32_t n_sectors, double max_dist, double *out);
+
+/* Singular viewshed, Alg. 1: the area (m^2) visible from grid cell (pov_row, pov_col), each
+ * line of sight passing through the POV. Host pointers. `out_mask` must be NULL (the per-cell
+ * mask is not provided by this version; a non-NULL mask returns TVS_EINVAL). */
+int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing,
+                          double obs_height, int32_t n_sectors, double max_dist,
+                          int32_t pov_row, int32_t pov_col, double *out_area, uint8_t *out_mask);
+
+/* Device-resident, stream-ordered total viewshed: d_dem and d_out are device pointers
+ * (rows*cols float / double). Elevations are not inspected on the host: the caller
+ * guarantees they are finite. */
+int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                             double obs_height, int32_t n_sectors, double max_dist,
+                             double *d_out, void *hip_stream);
+
+/* Device-resident singular viewshed: *d_area (device double) receives the area; d_mask must
+ * be NULL. */
+int tvs_singular_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                                double obs_height, int32_t n_sectors, double max_dist,
+                                int32_t pov_row, int32_t pov_col, double *d_area, uint8_t *d_mask,
+                                void *hip_stream);
+
+/* tvs_total_viewshed_async with variant `flags` (TVS_FLAG_*) and optional measurement. */
+int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                          double obs_height, int32_t n_sectors, double max_dist, double *d_out,
+                          uint32_t flags, tvs_stats *stats, void *hip_stream);
+
+/* tvs_singular_viewshed_async with variant flags (TVS_FLAG_SLOPE_F64 only) and, when
+ * d_ray_V is non-NULL, the per-line-of-sight ring sums: d_ray_V[2k] forward and [2k+1]
+ * backward of sector k, packed as U | (e << 30) (U whole rings in index^2 units including
+ * the POV ring, e in {0,1} clipped last ring of area rho^2 - K^2, K = ceil(rho) - 1). */
+int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                             double obs_height, int32_t n_sectors, double max_dist,
+                             int32_t pov_row, int32_t pov_col, uint32_t flags, double *d_area,
+                             uint32_t *d_ray_V, void *hip_stream);
+
+/* Shape of the skewed grid of sector `sector` (Section 4.1, Fig. 4b: one row per line of
+ * sight): rows t = t0 .. t0 + nrows - 1, columns 0 .. ncols - 1 of the 0..45 deg base frame. */
+int tvs_sector_shape(int32_t rows, int32_t cols, int32_t n_sectors, int32_t sector,
+                     int32_t *out_nrows, int32_t *out_ncols, int32_t *out_t0);
+
+/* Diagnostic: the per-sector skewed viewshed of Section 4.1 step 1c (skwVS before the
+ * back-projection) for one sector, computed by the same relocation and sweep kernels as
+ * the total viewshed. Host pointers; out_V is nrows x ncols (tvs_sector_shape) u32, each
+ * existing sample packed as U | (e << 30) (forward + backward: U whole rings including both
+ * POV rings, e in {0,1,2} clipped last rings); samples outside the grid are 0xFFFFFFFF. */
+int tvs_debug_sector_rays(const float *dem, int32_t rows, int32_t cols, double spacing,
+                          double obs_height, int32_t n_sectors, double max_dist, int32_t sector,
+                          uint32_t flags, uint32_t *out_V);
+
+/* Work of one total viewshed call, from the sector geometry alone: line-of-sight cell
+ * evaluations (per skewed row of nt samples, 2 * sum_{q<nt} min(q, K)) and POV-sector pairs. */
+int tvs_los_evals(int32_t rows, int32_t cols, double spacing, int32_t n_sectors, double max_dist,
+                  int64_t *out_evals, int64_t *out_pairs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBTVS_H */

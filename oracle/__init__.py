@@ -50,7 +50,8 @@ def lib():
         L.oracle_sector_V.argtypes = [f32p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_int, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]
         L.oracle_total.argtypes = [f32p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
-                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p]
+                                   C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, f64p, C.POINTER(C.c_longlong)]
+        L.oracle_threads.restype = C.c_int
         L.oracle_singular.argtypes = [f32p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
                                       C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double),
                                       C.c_void_p, C.c_void_p, C.c_void_p]
@@ -110,15 +111,21 @@ def sector_V(dem, spacing, obs_height, n, max_dist, k, prec=64):
     return info
 
 
-def total(dem, spacing, obs_height, n, max_dist, prec=64, window=None):
-    """Total viewshed in m^2. ``window`` = (r0, c0, nr, nc) restricts the cells computed."""
+def total(dem, spacing, obs_height, n, max_dist, prec=64, window=None, count=False):
+    """Total viewshed in m^2. ``window`` = (r0, c0, nr, nc) restricts the cells computed. With
+    ``count=True`` also returns the number of line-of-sight evaluations the oracle performed."""
     dem = _dem(dem)
     H, W = dem.shape
     r0, c0, nr, nc = window if window is not None else (0, 0, H, W)
     out = np.zeros((nr, nc), np.float64)
-    rc = lib().oracle_total(dem, H, W, spacing, obs_height, n, max_dist, prec, r0, c0, nr, nc, out)
+    ev = C.c_longlong()
+    rc = lib().oracle_total(dem, H, W, spacing, obs_height, n, max_dist, prec, r0, c0, nr, nc, out, C.byref(ev))
     _check(rc, "total")
-    return out
+    return (out, ev.value) if count else out
+
+
+def threads():
+    return lib().oracle_threads()
 
 
 def singular(dem, spacing, obs_height, n, max_dist, i0, j0, prec=64):

@@ -53,6 +53,7 @@
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math).
  */
 #include <limits.h>
+#include <omp.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -406,15 +407,16 @@ int oracle_sector_V(const float *dem, int rows, int cols, double dx, double h0, 
 /* Total viewshed (m^2) for the window of cells rows [r0, r0+nr), cols [c0, c0+nc)
  * (Alg. 4 with Alg. 9's back-projection and the per-sector scale). out is nr x nc. */
 int oracle_total(const float *dem, int rows, int cols, double dx, double h0, int n, double R, int prec,
-                 int r0, int c0, int nr, int nc, double *out)
+                 int r0, int c0, int nr, int nc, double *out, long long *out_evals)
 {
+    long long evals = 0;
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
     if (!out || (prec != 32 && prec != 64)) return ORC_EINVAL;
     if (r0 < 0 || c0 < 0 || nr < 0 || nc < 0 || r0 + nr > rows || c0 + nc > cols) return ORC_EINVAL;
     sector_t *S = make_sectors(rows, cols, dx, n, R);
     if (!S) return ORC_ENOMEM;
-#pragma omp parallel for schedule(dynamic, 1) collapse(2)
+#pragma omp parallel for schedule(dynamic, 1) collapse(2) reduction(+ : evals)
     for (int a = 0; a < nr; a++) {
         for (int b = 0; b < nc; b++) {
             int i = r0 + a, j = c0 + b;
@@ -427,11 +429,13 @@ int oracle_total(const float *dem, int rows, int cols, double dx, double h0, int
                 double rq = s->r[q];
                 ray_t va = pair_at(dem, s, ta, q, h0, prec);
                 double vx;
+                evals += va.M;
                 if (rq == 0.0) {
                     vx = va.cv;
                 } else {
                     ray_t vb = pair_at(dem, s, ta - 1, q, h0, prec);
                     vx = (1.0 - rq) * va.cv + rq * vb.cv;
+                    evals += vb.M;
                 }
                 acc += s->scale * vx;
             }
@@ -439,7 +443,20 @@ int oracle_total(const float *dem, int rows, int cols, double dx, double h0, int
         }
     }
     free_sectors(S, n);
+    if (out_evals) *out_evals = evals;
     return ORC_OK;
+}
+
+/* Threads the oracle's parallel loops use. */
+int oracle_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
 }
 
 /* Singular viewshed (Alg. 1): the area visible from grid cell (i0, j0), in m^2. The line

@@ -1,0 +1,199 @@
+"""libtvs: the sDEM total viewshed on MI355X (gfx950).
+
+Thin ctypes binding over ``libtvs.so`` (C ABI in ``include/libtvs.h``). Every step of the
+method runs in the library's HIP kernels; this module only marshals arguments. PyTorch is
+used for device memory and streams. There is no CPU fallback: if the library is missing the
+import of any entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+__all__ = [
+    "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
+    "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "Stats",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SO_PATH = os.path.join(_HERE, "libtvs.so")
+
+FLAG_SLOPE_F64 = 0x1
+FLAG_SWEEP_SCAN = 0x2
+FLAG_ACC_KAHAN32 = 0x4
+
+_STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
+
+
+class TvsError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("reloc_ms", C.c_double), ("sweep_ms", C.c_double), ("backproj_ms", C.c_double),
+        ("reloc_launches", C.c_int32), ("sweep_launches", C.c_int32), ("backproj_launches", C.c_int32),
+        ("chunks", C.c_int32), ("los_evals", C.c_int64), ("pov_sector_pairs", C.c_int64),
+        ("reloc_bytes", C.c_int64), ("sweep_bytes", C.c_int64), ("scratch_bytes", C.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+i32, f64, u32, vp = C.c_int32, C.c_double, C.c_uint32, C.c_void_p
+
+
+def lib():
+    """The loaded libtvs.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(SO_PATH):
+            raise ImportError(f"libtvs.so not found at {SO_PATH}; build it with "
+                              "`python -m paper_2003_02200_amd.build`")
+        L = C.CDLL(SO_PATH)
+        L.tvs_abi_version.restype = C.c_int
+        L.tvs_last_error.restype = C.c_char_p
+        L.tvs_total_viewshed.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp]
+        L.tvs_singular_viewshed.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, i32, vp, vp]
+        L.tvs_total_viewshed_async.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp, vp]
+        L.tvs_singular_viewshed_async.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, i32, vp, vp, vp]
+        L.tvs_total_viewshed_ex.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp, u32, C.POINTER(Stats), vp]
+        L.tvs_singular_viewshed_ex.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, i32, u32, vp, vp, vp]
+        L.tvs_sector_shape.argtypes = [i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
+        L.tvs_debug_sector_rays.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, u32, vp]
+        L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
+                     "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
+                     "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_los_evals"):
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().tvs_last_error()
+        raise TvsError(rc, msg.decode() if msg else "")
+
+
+def abi_version() -> int:
+    return lib().tvs_abi_version()
+
+
+def _is_torch_cuda(x) -> bool:
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        return False
+    return isinstance(x, torch.Tensor) and x.is_cuda
+
+
+def _stream_handle(stream):
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _host_dem(dem):
+    a = np.ascontiguousarray(dem, dtype=np.float32)
+    if a.ndim != 2:
+        raise ValueError("dem must be a 2-D grid")
+    return a
+
+
+def total_viewshed(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float = math.inf,
+                   flags: int = 0, stream=None, stats: bool = False):
+    """Total viewshed (m^2) of every cell.
+
+    ``dem``: numpy array (host call, synchronous) or CUDA float32 torch tensor (stream-ordered
+    on ``stream`` or the current stream; returns a float64 tensor on the same device). With
+    ``stats=True`` returns ``(out, Stats)``.
+    """
+    L = lib()
+    if _is_torch_cuda(dem):
+        import torch
+
+        if dem.dtype != torch.float32 or dem.dim() != 2:
+            raise ValueError("device dem must be a 2-D float32 tensor")
+        d = dem.contiguous()
+        H, W = d.shape
+        out = torch.empty((H, W), dtype=torch.float64, device=d.device)
+        st = Stats() if stats else None
+        with torch.cuda.device(d.device):
+            rc = L.tvs_total_viewshed_ex(C.c_void_p(d.data_ptr()), H, W, spacing, obs_height, n_sectors, max_dist,
+                                         C.c_void_p(out.data_ptr()), flags, C.byref(st) if st else None,
+                                         _stream_handle(stream))
+        _check(rc)
+        return (out, st) if stats else out
+    a = _host_dem(dem)
+    H, W = a.shape
+    if flags or stats:
+        import torch
+
+        out, st = total_viewshed(torch.from_numpy(a).cuda(), spacing, obs_height, n_sectors, max_dist, flags,
+                                 stream, True)
+        torch.cuda.synchronize()
+        res = out.cpu().numpy()
+        return (res, st) if stats else res
+    out = np.empty((H, W), np.float64)
+    _check(L.tvs_total_viewshed(a.ctypes.data_as(vp), H, W, spacing, obs_height, n_sectors, max_dist,
+                                out.ctypes.data_as(vp)))
+    return out
+
+
+def singular_viewshed(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float, pov_row: int,
+                      pov_col: int, flags: int = 0, rays: bool = False, stream=None):
+    """Area (m^2) visible from one cell. With ``rays=True`` also the 2n packed per-ray sums
+    (forward, backward per sector; U | e << 30). Host numpy grids are uploaded with torch."""
+    L = lib()
+    import torch
+
+    d = dem if _is_torch_cuda(dem) else torch.from_numpy(_host_dem(dem)).cuda()
+    if d.dtype != torch.float32 or d.dim() != 2:
+        raise ValueError("dem must be a 2-D float32 grid")
+    d = d.contiguous()
+    H, W = d.shape
+    area = torch.empty(1, dtype=torch.float64, device=d.device)
+    rv = torch.empty(2 * n_sectors, dtype=torch.int32, device=d.device) if rays else None
+    with torch.cuda.device(d.device):
+        rc = L.tvs_singular_viewshed_ex(C.c_void_p(d.data_ptr()), H, W, spacing, obs_height, n_sectors, max_dist,
+                                        pov_row, pov_col, flags, C.c_void_p(area.data_ptr()),
+                                        C.c_void_p(rv.data_ptr()) if rays else None, _stream_handle(stream))
+    _check(rc)
+    torch.cuda.current_stream(d.device).synchronize() if stream is None else stream.synchronize()
+    a = float(area.item())
+    if rays:
+        return a, rv.cpu().numpy().view(np.uint32).copy()
+    return a
+
+
+def sector_shape(rows: int, cols: int, n_sectors: int, sector: int):
+    nr, nc, t0 = i32(), i32(), i32()
+    _check(lib().tvs_sector_shape(rows, cols, n_sectors, sector, C.byref(nr), C.byref(nc), C.byref(t0)))
+    return nr.value, nc.value, t0.value
+
+
+def debug_sector_rays(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float, sector: int,
+                      flags: int = 0) -> np.ndarray:
+    """Per-sector skewed viewshed (nrows x ncols u32, U | e << 30; 0xFFFFFFFF = no sample)."""
+    a = _host_dem(dem)
+    H, W = a.shape
+    nr, nc, _ = sector_shape(H, W, n_sectors, sector)
+    out = np.empty((nr, nc), np.uint32)
+    _check(lib().tvs_debug_sector_rays(a.ctypes.data_as(vp), H, W, spacing, obs_height, n_sectors, max_dist,
+                                       sector, flags, out.ctypes.data_as(vp)))
+    return out
+
+
+def los_evals(rows: int, cols: int, spacing: float, n_sectors: int, max_dist: float):
+    ev, pr = C.c_int64(), C.c_int64()
+    _check(lib().tvs_los_evals(rows, cols, spacing, n_sectors, max_dist, C.byref(ev), C.byref(pr)))
+    return ev.value, pr.value

@@ -1,0 +1,537 @@
+// tvs_api.hip -- C ABI of libtvs: validation, the per-sector plan, scratch management and the
+// launch sequence of the sDEM total viewshed (Section 4.1 steps 1a-1d with the three kernels
+// of Section 4.2) and of the singular viewshed (Alg. 1).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <cstring>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/libtvs.h"
+#include "tvs_geom.h"
+#include "tvs_internal.h"
+
+using namespace tvs;
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(TVS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// One sector of the plan (host side).
+struct Sector {
+    int kase, Hx, Wx;
+    double T;      // tan s'
+    double rho;    // max_dist cos s' / spacing
+    int K;         // last target index in range (TVS_K_UNBOUNDED when max_dist never binds)
+    double scale;  // (pi / 2n) spacing^2 / cos^2 s'
+    double clip;   // rho^2 - K^2
+    int t0, nrows;
+};
+
+// Sector k of n (Section 3.1 axes; base-frame cases of the kernels' 0..45 deg range).
+Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
+    Sector s;
+    long long num, den;
+    if (4LL * k <= n) {
+        s.kase = 0; num = k; den = n;
+    } else if (4LL * k <= 2LL * n) {
+        s.kase = 1; num = n - 2LL * k; den = 2LL * n;
+    } else if (4LL * k < 3LL * n) {
+        s.kase = 2; num = 2LL * k - n; den = 2LL * n;
+    } else {
+        s.kase = 3; num = n - k; den = n;
+    }
+    frame_dims(s.kase, H, W, s.Hx, s.Wx);
+    const double sp = (M_PI * (double)num) / (double)den;
+    if (num == 0) s.T = 0.0;
+    else if (4 * num == den) s.T = 1.0;
+    else s.T = tan(sp);
+    const double c = cos(sp);
+    s.scale = (M_PI / (2.0 * (double)n)) * (dx * dx) / (c * c);
+    s.K = TVS_K_UNBOUNDED;
+    s.clip = 0.0;
+    if (isinf(R)) {
+        s.rho = INFINITY;
+    } else {
+        s.rho = (R * c) / dx;
+        const double kk = ceil(s.rho) - 1.0;
+        if (kk < (double)TVS_K_UNBOUNDED) {
+            s.K = (int)kk;
+            s.clip = s.rho * s.rho - (double)s.K * (double)s.K;
+        }
+    }
+    int dmax;
+    double rmax;
+    col_offset(s.T, s.Wx - 1, dmax, rmax);
+    s.t0 = -dmax - 1;
+    s.nrows = s.Hx - s.t0;
+    return s;
+}
+
+int check_scalars(int rows, int cols, double dx, double h0, int n, double R) {
+    if (rows < 1 || cols < 1) return fail(TVS_EINVAL, "rows and cols must be >= 1 (got %d x %d)", rows, cols);
+    if (rows > TVS_MAX_SIDE || cols > TVS_MAX_SIDE)
+        return fail(TVS_ERANGE, "grid %d x %d exceeds the %d-cell side limit", rows, cols, TVS_MAX_SIDE);
+    if (!(dx > 0.0) || !isfinite(dx)) return fail(TVS_EINVAL, "spacing must be finite and > 0");
+    if (!isfinite(h0)) return fail(TVS_EINVAL, "obs_height must be finite");
+    if (n < 1 || n > TVS_MAX_SECTORS) return fail(TVS_EINVAL, "n_sectors must be in [1, %d]", TVS_MAX_SECTORS);
+    if (isnan(R) || !(R > 0.0)) return fail(TVS_EINVAL, "max_dist must be > 0 (INFINITY allowed)");
+    return TVS_OK;
+}
+
+int check_host_dem(const float *dem, int rows, int cols) {
+    const int64_t N = (int64_t)rows * cols;
+    for (int64_t x = 0; x < N; ++x)
+        if (!isfinite(dem[x]))
+            return fail(TVS_EINVAL, "non-finite elevation at cell (%lld, %lld)", (long long)(x / cols),
+                        (long long)(x % cols));
+    return TVS_OK;
+}
+
+// Sector k's row extents on the host (same predicates as the kernels) -> evals / pairs.
+void count_sector(const Sector &s, int64_t &evals, int64_t &pairs) {
+    for (int ri = 0; ri < s.nrows; ++ri) {
+        const int t = s.t0 + ri;
+        const int nt = row_last(s.T, t, s.Hx, s.Wx) - row_first(s.T, t, s.Hx, s.Wx) + 1;
+        if (nt <= 0) continue;
+        pairs += nt;
+        const int64_t K = s.K;
+        if (K >= nt - 1) {
+            evals += (int64_t)nt * (nt - 1);
+        } else {
+            evals += 2 * (K * (K - 1) / 2 + (int64_t)(nt - K) * K);
+        }
+    }
+}
+
+int pitch_of(int H, int W) { return ((std::max(H, W) + 63) / 64) * 64; }
+
+size_t scratch_budget() {
+    const char *env = getenv("TVS_SCRATCH_MB");
+    if (env && *env) return (size_t)atoll(env) << 20;
+    size_t freeb = 0, total = 0;
+    if (hipMemGetInfo(&freeb, &total) != hipSuccess) return (size_t)4 << 30;
+    return std::min(freeb / 2, (size_t)16 << 30);
+}
+
+// Groups of consecutive sectors: at most TVS_CHUNK each, scratch within the budget.
+struct Chunk {
+    int k0, k1;        // [k0, k1)
+    size_t bytes;      // skewed buffers of the chunk
+    int maxRows, maxWx;
+};
+
+std::vector<Chunk> make_chunks(const std::vector<Sector> &S, size_t elem, int pitch, size_t budget) {
+    std::vector<Chunk> out;
+    int k = 0;
+    const int n = (int)S.size();
+    while (k < n) {
+        Chunk c{k, k, 0, 0, 0};
+        while (c.k1 < n && c.k1 - c.k0 < TVS_CHUNK) {
+            const size_t b = (size_t)S[c.k1].nrows * pitch * (elem + sizeof(uint32_t));
+            if (c.k1 > c.k0 && c.bytes + b > budget) break;
+            c.bytes += b;
+            c.maxRows = std::max(c.maxRows, S[c.k1].nrows);
+            c.maxWx = std::max(c.maxWx, S[c.k1].Wx);
+            ++c.k1;
+        }
+        out.push_back(c);
+        k = c.k1;
+    }
+    return out;
+}
+
+ChunkArgs chunk_args(const std::vector<Sector> &S, const Chunk &c, int H, int W, int pitch, double h0) {
+    ChunkArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nsec = c.k1 - c.k0;
+    a.H = H;
+    a.W = W;
+    a.pitch = pitch;
+    a.h0 = h0;
+    a.h0f = (float)h0;
+    a.k_base = c.k0;
+    int64_t off = 0;
+    for (int x = 0; x < a.nsec; ++x) {
+        const Sector &s = S[c.k0 + x];
+        SecDev &d = a.s[x];
+        d.T = s.T;
+        d.scale = s.scale;
+        d.clip = s.clip;
+        d.off = off;
+        d.kase = s.kase;
+        d.K = s.K;
+        d.t0 = s.t0;
+        d.nrows = s.nrows;
+        off += (int64_t)s.nrows * pitch;
+    }
+    return a;
+}
+
+// Stream-ordered device scratch, released when the stream reaches the free.
+struct Scratch {
+    void *p = nullptr;
+    hipStream_t st = nullptr;
+    ~Scratch() {
+        if (p) (void)hipFreeAsync(p, st);
+    }
+};
+
+// Timing of launches with events on the call's stream (only when stats are requested).
+struct Timer {
+    bool on = false;
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;  // 0 reloc, 1 sweep, 2 backproj
+    ~Timer() {
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+    hipError_t mark() {
+        if (!on) return hipSuccess;
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+        return hipEventRecord(e, st);
+    }
+    hipError_t begin(int k) {
+        if (on) kind.push_back(k);
+        return mark();
+    }
+};
+
+void pool_keep_memory(int dev) {
+    static bool done[64] = {false};
+    if (dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[dev] = true;
+}
+
+int lds_limit(int dev) {
+    int v = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
+        v = 65536;
+        (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    }
+    return v;
+}
+
+// The total viewshed on the device: one chunk of sectors at a time, relocation -> sweep ->
+// back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
+int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
+              uint32_t flags, tvs_stats *stats, hipStream_t st, int debug_sector, uint32_t *d_debugV,
+              int *debug_pitch) {
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
+    const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
+    const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    pool_keep_memory(dev);
+    const int pitch = pitch_of(H, W);
+    const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    if (sweep_lds_bytes(std::max(H, W), f64) > (size_t)lds_limit(dev))
+        return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)",
+                    std::max(H, W), f64 ? "double" : "float", lds_limit(dev));
+
+    std::vector<Sector> S;
+    if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));
+    else
+        for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, scratch_budget());
+    size_t maxChunk = 0;
+    for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
+    const int tabN = std::max(H, W) + 1;
+    const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
+    const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
+    const size_t total = tabBytes + kahanBytes + 256 * 4 + maxChunk;
+
+    Scratch scr;
+    scr.st = st;
+    if (hipMallocAsync(&scr.p, total, st) != hipSuccess) {
+        (void)hipGetLastError();
+        scr.p = nullptr;
+        return fail(TVS_ENOMEM, "device scratch of %zu bytes not available", total);
+    }
+    char *base = (char *)scr.p;
+    auto carve = [&](size_t b) {
+        char *p = base;
+        base += (b + 255) & ~(size_t)255;
+        return (void *)p;
+    };
+    float2 *tab32 = (float2 *)carve((size_t)tabN * sizeof(float2));
+    double2 *tab64 = (double2 *)carve((size_t)tabN * sizeof(double2));
+    float *ksum = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
+    float *kc = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
+    char *skwV = (char *)carve(maxChunk);
+
+    Timer tm;
+    tm.on = stats != nullptr;
+    tm.st = st;
+    HIPCHK(launch_divtab(tab32, tab64, tabN, st));
+    int64_t evals = 0, pairs = 0;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const Chunk &c = chunks[ci];
+        ChunkArgs a = chunk_args(S, c, H, W, pitch, h0);
+        const int64_t elems = (int64_t)(c.bytes / (elem + sizeof(uint32_t)));
+        void *skw = skwV;
+        uint32_t *V = (uint32_t *)(skwV + (size_t)elems * elem);
+        if (d_debugV) HIPCHK(launch_fill_u32(V, elems, 0xFFFFFFFFu, st));
+        HIPCHK(tm.begin(0));
+        HIPCHK(launch_relocate(a, c.maxWx, c.maxRows, d_dem, skw, f64, st));
+        HIPCHK(tm.mark());
+        HIPCHK(tm.begin(1));
+        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, st));
+        HIPCHK(tm.mark());
+        if (d_debugV) {
+            const Sector &s = S[0];
+            HIPCHK(hipMemcpy2DAsync(d_debugV, (size_t)s.Wx * 4, V, (size_t)pitch * 4, (size_t)s.Wx * 4,
+                                    (size_t)s.nrows, hipMemcpyDeviceToDevice, st));
+            if (debug_pitch) *debug_pitch = pitch;
+            continue;
+        }
+        HIPCHK(tm.begin(2));
+        HIPCHK(launch_backproj(a, V, d_out, ksum, kc, ci == 0, ci + 1 == chunks.size(), st));
+        HIPCHK(tm.mark());
+        if (stats)
+            for (int k = c.k0; k < c.k1; ++k) count_sector(S[k], evals, pairs);
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        if (!tm.ev.empty()) HIPCHK(hipEventSynchronize(tm.ev.back()));
+        for (size_t x = 0; x < tm.kind.size(); ++x) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, tm.ev[2 * x], tm.ev[2 * x + 1]));
+            if (tm.kind[x] == 0) { stats->reloc_ms += ms; stats->reloc_launches++; }
+            else if (tm.kind[x] == 1) { stats->sweep_ms += ms; stats->sweep_launches++; }
+            else { stats->backproj_ms += ms; stats->backproj_launches++; }
+        }
+        stats->chunks = (int32_t)chunks.size();
+        stats->los_evals = evals;
+        stats->pov_sector_pairs = pairs;
+        stats->reloc_bytes = pairs * (int64_t)(4 + elem);
+        stats->sweep_bytes = pairs * (int64_t)(elem + 4);
+        stats->scratch_bytes = (int64_t)total;
+    }
+    return TVS_OK;
+}
+
+int run_singular(const float *d_dem, int H, int W, double dx, double h0, int n, double R, int pi, int pj,
+                 uint32_t flags, double *d_area, uint32_t *d_rayV, hipStream_t st) {
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    pool_keep_memory(dev);
+    Scratch scr;
+    scr.st = st;
+    uint32_t *rayV = d_rayV;
+    if (!rayV) {
+        if (hipMallocAsync(&scr.p, (size_t)2 * n * sizeof(uint32_t), st) != hipSuccess) {
+            (void)hipGetLastError();
+            scr.p = nullptr;
+            return fail(TVS_ENOMEM, "device scratch for %d lines of sight not available", 2 * n);
+        }
+        rayV = (uint32_t *)scr.p;
+    }
+    std::vector<Sector> S;
+    for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+    const int pitch = pitch_of(H, W);
+    for (int k0 = 0; k0 < n; k0 += TVS_CHUNK) {
+        Chunk c{k0, std::min(n, k0 + TVS_CHUNK), 0, 0, 0};
+        ChunkArgs a = chunk_args(S, c, H, W, pitch, h0);
+        a.pov_i = pi;
+        a.pov_j = pj;
+        HIPCHK(launch_singular(a, d_dem, rayV, f64, st));
+        HIPCHK(launch_singular_sum(a, rayV, d_area, k0 == 0, st));
+    }
+    return TVS_OK;
+}
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    hipError_t alloc(size_t n) { return hipMalloc((void **)&p, n * sizeof(T)); }
+};
+
+}  // namespace
+
+extern "C" {
+
+int tvs_abi_version(void) { return TVS_ABI_VERSION; }
+
+const char *tvs_last_error(void) { return g_err; }
+
+int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                          int32_t n_sectors, double max_dist, double *d_out, uint32_t flags, tvs_stats *stats,
+                          void *hip_stream) {
+    g_err[0] = 0;
+    if (!d_dem || !d_out) return fail(TVS_EINVAL, "null dem or out pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_ACC_KAHAN32))
+        return fail(TVS_EINVAL, "unknown flags 0x%x", flags);
+    return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, flags, stats,
+                     (hipStream_t)hip_stream, -1, nullptr, nullptr);
+}
+
+int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                             int32_t n_sectors, double max_dist, double *d_out, void *hip_stream) {
+    return tvs_total_viewshed_ex(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, 0u, nullptr,
+                                 hip_stream);
+}
+
+int tvs_total_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                       int32_t n_sectors, double max_dist, double *out) {
+    g_err[0] = 0;
+    if (!dem || !out) return fail(TVS_EINVAL, "null dem or out pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if ((rc = check_host_dem(dem, rows, cols))) return rc;
+    const size_t N = (size_t)rows * cols;
+    DevBuf<float> d_dem;
+    DevBuf<double> d_out;
+    if (d_dem.alloc(N) != hipSuccess || d_out.alloc(N) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TVS_ENOMEM, "device buffers for a %d x %d grid not available", rows, cols);
+    }
+    HIPCHK(hipMemcpy(d_dem.p, dem, N * sizeof(float), hipMemcpyHostToDevice));
+    rc = run_total(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out.p, 0u, nullptr, nullptr,
+                   -1, nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(nullptr));
+    HIPCHK(hipMemcpy(out, d_out.p, N * sizeof(double), hipMemcpyDeviceToHost));
+    return TVS_OK;
+}
+
+int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                             int32_t n_sectors, double max_dist, int32_t pov_row, int32_t pov_col, uint32_t flags,
+                             double *d_area, uint32_t *d_ray_V, void *hip_stream) {
+    g_err[0] = 0;
+    if (!d_dem || !d_area) return fail(TVS_EINVAL, "null dem or area pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
+        return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, rows, cols);
+    if (flags & ~TVS_FLAG_SLOPE_F64) return fail(TVS_EINVAL, "unsupported flags 0x%x for the singular viewshed", flags);
+    return run_singular(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, flags,
+                        d_area, d_ray_V, (hipStream_t)hip_stream);
+}
+
+int tvs_singular_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                                int32_t n_sectors, double max_dist, int32_t pov_row, int32_t pov_col,
+                                double *d_area, uint8_t *d_mask, void *hip_stream) {
+    if (d_mask) return fail(TVS_EINVAL, "the per-cell singular mask is not provided; pass NULL");
+    return tvs_singular_viewshed_ex(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col,
+                                    0u, d_area, nullptr, hip_stream);
+}
+
+int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                          int32_t n_sectors, double max_dist, int32_t pov_row, int32_t pov_col, double *out_area,
+                          uint8_t *out_mask) {
+    g_err[0] = 0;
+    if (!dem || !out_area) return fail(TVS_EINVAL, "null dem or area pointer");
+    if (out_mask) return fail(TVS_EINVAL, "the per-cell singular mask is not provided; pass NULL");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
+        return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, rows, cols);
+    if ((rc = check_host_dem(dem, rows, cols))) return rc;
+    const size_t N = (size_t)rows * cols;
+    DevBuf<float> d_dem;
+    DevBuf<double> d_area;
+    if (d_dem.alloc(N) != hipSuccess || d_area.alloc(1) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TVS_ENOMEM, "device buffers for a %d x %d grid not available", rows, cols);
+    }
+    HIPCHK(hipMemcpy(d_dem.p, dem, N * sizeof(float), hipMemcpyHostToDevice));
+    rc = run_singular(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, 0u, d_area.p,
+                      nullptr, nullptr);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(nullptr));
+    HIPCHK(hipMemcpy(out_area, d_area.p, sizeof(double), hipMemcpyDeviceToHost));
+    return TVS_OK;
+}
+
+int tvs_sector_shape(int32_t rows, int32_t cols, int32_t n_sectors, int32_t sector, int32_t *out_nrows,
+                     int32_t *out_ncols, int32_t *out_t0) {
+    g_err[0] = 0;
+    if (!out_nrows || !out_ncols || !out_t0) return fail(TVS_EINVAL, "null output pointer");
+    int rc = check_scalars(rows, cols, 1.0, 0.0, n_sectors, INFINITY);
+    if (rc) return rc;
+    if (sector < 0 || sector >= n_sectors) return fail(TVS_EINVAL, "sector %d outside [0, %d)", sector, n_sectors);
+    const Sector s = plan_sector(sector, n_sectors, rows, cols, 1.0, INFINITY);
+    *out_nrows = s.nrows;
+    *out_ncols = s.Wx;
+    *out_t0 = s.t0;
+    return TVS_OK;
+}
+
+int tvs_debug_sector_rays(const float *dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                          int32_t n_sectors, double max_dist, int32_t sector, uint32_t flags, uint32_t *out_V) {
+    g_err[0] = 0;
+    if (!dem || !out_V) return fail(TVS_EINVAL, "null dem or out_V pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (sector < 0 || sector >= n_sectors) return fail(TVS_EINVAL, "sector %d outside [0, %d)", sector, n_sectors);
+    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN)) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
+    if ((rc = check_host_dem(dem, rows, cols))) return rc;
+    const Sector s = plan_sector(sector, n_sectors, rows, cols, spacing, max_dist);
+    const size_t N = (size_t)rows * cols;
+    const size_t NV = (size_t)s.nrows * s.Wx;
+    DevBuf<float> d_dem;
+    DevBuf<uint32_t> d_V;
+    if (d_dem.alloc(N) != hipSuccess || d_V.alloc(NV) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TVS_ENOMEM, "device buffers not available");
+    }
+    HIPCHK(hipMemcpy(d_dem.p, dem, N * sizeof(float), hipMemcpyHostToDevice));
+    int pitch = 0;
+    rc = run_total(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, nullptr, flags, nullptr, nullptr,
+                   sector, d_V.p, &pitch);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(nullptr));
+    HIPCHK(hipMemcpy(out_V, d_V.p, NV * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    return TVS_OK;
+}
+
+int tvs_los_evals(int32_t rows, int32_t cols, double spacing, int32_t n_sectors, double max_dist, int64_t *out_evals,
+                  int64_t *out_pairs) {
+    g_err[0] = 0;
+    if (!out_evals || !out_pairs) return fail(TVS_EINVAL, "null output pointer");
+    int rc = check_scalars(rows, cols, spacing, 0.0, n_sectors, max_dist);
+    if (rc) return rc;
+    int64_t ev = 0, pr = 0;
+    for (int k = 0; k < n_sectors; ++k) count_sector(plan_sector(k, n_sectors, rows, cols, spacing, max_dist), ev, pr);
+    *out_evals = ev;
+    *out_pairs = pr;
+    return TVS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// tvs_internal.h -- launch-level types of libtvs (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tvs_geom.h"
+
+// Sectors processed by one group of launches; their parameters travel as kernel arguments
+// (48 x 48 B), so the library needs no host-to-device copy besides the caller's data.
+#define TVS_CHUNK 48
+// Sentinel columns on each side of a skewed row held in LDS by the sweep: a wavefront's 64
+// lines of sight all stop at the same step, lanes that run past their row end read these.
+#define TVS_SWEEP_PAD 64
+
+namespace tvs {
+
+struct SecDev {
+    double T;       // tan s'
+    double scale;   // m^2 per index^2 unit of a half-sector ring: (pi / 2n) dx^2 / cos^2 s'
+    double clip;    // area of the clipped last ring, index^2 units: rho^2 - K^2 (0 if unbounded)
+    int64_t off;    // element offset of the sector's skewed buffers
+    int32_t kase;   // base-frame case 0..3
+    int32_t K;      // last target index in range, TVS_K_UNBOUNDED if max_dist never binds
+    int32_t t0;     // first skewed row
+    int32_t nrows;  // skewed rows t0 .. t0 + nrows - 1 (the last is Hx - 1)
+};
+
+struct ChunkArgs {
+    SecDev s[TVS_CHUNK];
+    int32_t nsec;   // sectors in this chunk
+    int32_t H, W;   // grid dims
+    int32_t pitch;  // row pitch (elements) of the skewed buffers
+    double h0;      // observer height
+    float h0f;      // observer height rounded to float
+    int32_t k_base; // global index of s[0]
+    int32_t pov_i, pov_j;  // singular POV (grid cell)
+    int32_t pad0, pad1;
+};
+
+// Launchers (tvs_kernels.hip). All enqueue on `st` and return the launch status.
+hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st);
+hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw,
+                           bool f64, hipStream_t st);
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
+                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, hipStream_t st);
+hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum,
+                           float *kahan_c, int first, int last, hipStream_t st);
+hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, hipStream_t st);
+hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first,
+                               hipStream_t st);
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+size_t sweep_lds_bytes(int maxWx, bool f64);
+
+}  // namespace tvs

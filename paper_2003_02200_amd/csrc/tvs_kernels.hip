@@ -1,0 +1,618 @@
+// tvs_kernels.hip -- gfx950 kernels of libtvs, the sDEM total viewshed.
+//
+// Per group of sectors (Section 4.1 steps 1a-1d, Section 4.2):
+//   k_relocate  DEM -> skwDEM (Alg. 6). Written as a gather: each skewed sample is produced
+//               by exactly one thread as (1-r_j) X[u][j] + r_j X[u+1][j], from a tile of the
+//               base frame staged in LDS by coalesced row reads of the DEM (transposed on the
+//               way in for the 45..135 deg axes). Alg. 6's scatter with two "+=" per DEM
+//               cell has adjacent threads updating the same skwDEM element; a gather has one
+//               writer per output.
+//   k_sweep     skwDEM -> skwVS (Alg. 7 / Alg. 8). One workgroup holds one skewed row (one
+//               line of sight of every POV on it) in LDS. A wavefront owns 64 consecutive
+//               POVs, one per lane, and steps all 64 lines of sight together: step m reads
+//               z[q+m] (forward) or z[q-m] (backward), forms the slope (z - h)/m, compares it
+//               with the lane's running maximum and adds the ring weight 2m+1 when visible.
+//               The ring sums are integers (Alg. 8's dd^2 - open_dd^2 telescopes to a sum of
+//               2m+1 over visible samples), so they are kept exactly in u32.
+//   k_backproj  skwVS -> VS (Alg. 9): each DEM cell blends the two skewed samples around it,
+//               scales by the half-sector ring area (Alg. 1's pi/ns, Alg. 7's 1/cos^2) and
+//               accumulates over sectors in double.
+// and the singular viewshed (Alg. 1-3) as a ray scan: one wavefront per line of sight, lanes =
+// 64 consecutive targets, the horizon carried by a wavefront prefix-max.
+//
+// Floating point: the float path rounds the interpolated elevation to float, forms h = z + h0,
+// d = z - h and the slope as the correctly rounded quotient d / m (reciprocal table, one
+// product and one FMA correction; exact for every integer m in range), and compares in float.
+// The double path does the same steps in double. Explicit _rn intrinsics keep the compiler
+// from contracting any step into an FMA.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "tvs_geom.h"
+#include "tvs_internal.h"
+
+namespace tvs {
+
+// ----------------------------------------------------------------------------- numerics
+
+__device__ __forceinline__ float slope_div(float d, float2 t) {  // t = {m, RN(1/m)}
+    float q = __fmul_rn(d, t.y);
+    float r = __fmaf_rn(-q, t.x, d);
+    return __fmaf_rn(r, t.y, q);
+}
+__device__ __forceinline__ double slope_div(double d, double2 t) {
+    double q = __dmul_rn(d, t.y);
+    double r = __fma_rn(-q, t.x, d);
+    return __fma_rn(r, t.y, q);
+}
+__device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
+__device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
+__device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
+__device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(a, b); }
+
+// One visibility step: vis = th > mx (strict), bits = 2 bits + vis, mx = max(mx, th). The
+// compare writes VCC and the add-with-carry takes it as carry-in (two VALU instructions; the
+// compiler does not form this pair from C++). max equals "vis ? th : mx" here: slopes are
+// never NaN except on sentinel lanes, where both keep mx.
+__device__ __forceinline__ void vis_step(float th, float &mx, uint32_t &bits) {
+    asm("v_cmp_gt_f32 vcc, %1, %2\n\t"
+        "v_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(bits)
+        : "v"(th), "v"(mx)
+        : "vcc");
+    mx = __builtin_fmaxf(mx, th);
+}
+__device__ __forceinline__ void vis_step(double th, double &mx, uint32_t &bits) {
+    asm("v_cmp_gt_f64 vcc, %1, %2\n\t"
+        "v_addc_co_u32 %0, vcc, %0, %0, vcc"
+        : "+v"(bits)
+        : "v"(th), "v"(mx)
+        : "vcc");
+    mx = __builtin_fmax(mx, th);
+}
+
+template <typename Tz> struct Tab;
+template <> struct Tab<float> { using type = float2; };
+template <> struct Tab<double> { using type = double2; };
+
+template <typename Tz> __device__ __forceinline__ Tz neg_inf();
+template <> __device__ __forceinline__ float neg_inf<float>() { return -__builtin_inff(); }
+template <> __device__ __forceinline__ double neg_inf<double>() { return -__builtin_inf(); }
+
+// Interpolated elevation (double) of the base-frame sample at row u + r of column q, rows
+// clamped to [0, Hx-1]; `row(v)` returns X[v][q] as float.
+template <typename RowFn>
+__device__ __forceinline__ double interp(int u, double r, int Hx, RowFn row) {
+    const int ua = min(max(u, 0), Hx - 1);
+    const int ub = min(max(u + 1, 0), Hx - 1);
+    const float a = row(ua);
+    if (r == 0.0 || ua == ub) return (double)a;
+    const float b = row(ub);
+    const double w = __dsub_rn(1.0, r);
+    return __dadd_rn(__dmul_rn(w, (double)a), __dmul_rn(r, (double)b));
+}
+
+// ------------------------------------------------------------------- wavefront primitives
+// DPP lane moves of the GFX9 family (row_shr, row_bcast, wave_shr). Lanes without a source
+// keep `old`.
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ float dpp_mov(float old, float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(old), __float_as_int(x), CTRL,
+                                                      ROW_MASK, 0xf, false));
+}
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ double dpp_mov(double old, double x) {
+    const int2 o = *reinterpret_cast<const int2 *>(&old);
+    const int2 v = *reinterpret_cast<const int2 *>(&x);
+    int2 res;
+    res.x = __builtin_amdgcn_update_dpp(o.x, v.x, CTRL, ROW_MASK, 0xf, false);
+    res.y = __builtin_amdgcn_update_dpp(o.y, v.y, CTRL, ROW_MASK, 0xf, false);
+    return *reinterpret_cast<const double *>(&res);
+}
+template <typename T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+
+// Inclusive prefix maximum over the 64 lanes (lane l gets max of lanes 0..l).
+template <typename T>
+__device__ __forceinline__ T wave_prefix_max(T x) {
+    const T lo = neg_inf<T>();
+    x = vmax(x, dpp_mov<0x111>(lo, x));        // row_shr:1
+    x = vmax(x, dpp_mov<0x112>(lo, x));        // row_shr:2
+    x = vmax(x, dpp_mov<0x114>(lo, x));        // row_shr:4
+    x = vmax(x, dpp_mov<0x118>(lo, x));        // row_shr:8
+    x = vmax(x, dpp_mov<0x142, 0xa>(lo, x));   // row_bcast:15 into rows 1 and 3
+    x = vmax(x, dpp_mov<0x143, 0xc>(lo, x));   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+// Lane l gets lane l-1's value; lane 0 gets `old` (wave_shr:1).
+template <typename T>
+__device__ __forceinline__ T wave_shift_up(T old, T x) { return dpp_mov<0x138>(old, x); }
+
+template <typename T>
+__device__ __forceinline__ T lane63(T x) {
+    if constexpr (sizeof(T) == 4) {
+        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 63));
+    } else {
+        int2 v = *reinterpret_cast<const int2 *>(&x);
+        v.x = __builtin_amdgcn_readlane(v.x, 63);
+        v.y = __builtin_amdgcn_readlane(v.y, 63);
+        return *reinterpret_cast<const double *>(&v);
+    }
+}
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ------------------------------------------------------------------------ small kernels
+
+__global__ void k_divtab(float2 *tab32, double2 *tab64, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const float mf = (float)m;
+    const double md = (double)m;
+    tab32[m] = make_float2(mf, m ? __fdiv_rn(1.0f, mf) : 0.0f);
+    tab64[m] = make_double2(md, m ? __ddiv_rn(1.0, md) : 0.0);
+}
+
+__global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = i; x < n; x += stride) p[x] = v;
+}
+
+// --------------------------------------------------------------------------- relocation
+// Output tile: 64 skewed rows x 64 columns of one sector per 256-thread workgroup. The base
+// frame rows it needs, [t + d_j, t + d_j + 1] over the tile, span at most 64 + 66 rows; they
+// are staged in LDS (row pitch 65 words so the transposed stores of cases 1/2 spread over
+// all banks), then every thread interpolates its column for 16 rows and stores them along
+// the skewed row (64 consecutive columns per wavefront).
+constexpr int RL_TW = 64;
+constexpr int RL_TH = 64;
+constexpr int RL_LP = RL_TW + 1;
+constexpr int RL_MAXR = RL_TH + RL_TW + 3;
+
+template <typename Tz>
+__global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float *__restrict__ dem,
+                                                  Tz *__restrict__ skw) {
+    __shared__ float tile[RL_MAXR * RL_LP];
+    const SecDev &s = a.s[blockIdx.z];
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    const int j0 = blockIdx.x * RL_TW;
+    const int r0 = blockIdx.y * RL_TH;
+    if (j0 >= Wx || r0 >= s.nrows) return;
+    const int tb = s.t0 + r0;
+    const int te = min(tb + RL_TH - 1, Hx - 1);
+    const int jl = min(j0 + RL_TW - 1, Wx - 1);
+    int dlo, dhi;
+    double rlo, rhi;
+    col_offset(s.T, j0, dlo, rlo);
+    col_offset(s.T, jl, dhi, rhi);
+    // no sample of the tile exists: every column's rows lie below -1 or above Hx-1
+    if (te + dhi < -1 || tb + dlo > Hx - 1) return;
+    const int ua = min(max(tb + dlo, 0), Hx - 1);
+    const int ub = min(max(te + dhi + 1, 0), Hx - 1);
+    const int nr = ub - ua + 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int ncol = jl - j0 + 1;
+    if (s.kase == 0 || s.kase == 3) {
+        // base-frame rows are grid rows (reversed for case 3): coalesced along the row
+        if (lane < ncol) {
+            for (int rr = wv; rr < nr; rr += 4)
+                tile[rr * RL_LP + lane] = dem[frame_index(s.kase, a.W, ua + rr, j0 + lane)];
+        }
+    } else {
+        // base-frame columns are grid rows: read along them and transpose into LDS
+        for (int c = wv; c < ncol; c += 4)
+            for (int rr = lane; rr < nr; rr += 64)
+                tile[rr * RL_LP + c] = dem[frame_index(s.kase, a.W, ua + rr, j0 + c)];
+    }
+    __syncthreads();
+    if (lane >= ncol) return;
+    const int q = j0 + lane;
+    int d;
+    double r;
+    col_offset(s.T, q, d, r);
+    Tz *out = skw + s.off + q;
+    for (int rr = wv; rr <= te - tb; rr += 4) {
+        const int u = tb + rr + d;
+        if (!sample_exists(u, r, Hx)) continue;
+        const double z = interp(u, r, Hx, [&](int v) { return tile[(v - ua) * RL_LP + lane]; });
+        out[(int64_t)(r0 + rr) * a.pitch] = (Tz)z;
+    }
+}
+
+// -------------------------------------------------------------------------------- sweep
+
+// One direction of the lines of sight of a wavefront's 64 POVs. `zp` points at the lane's
+// POV in the LDS row, `mb` is the last step any lane of the wavefront needs (lanes whose
+// row ends earlier read -inf sentinels, which are never visible). Steps m < K add the whole
+// ring 2m+1 to U; the step m = K (the ring clipped at rho) is returned as 0/1.
+//
+// Steps run in blocks of 32: each step shifts its visibility bit into `bits` (step m0+s lands
+// in bit 31-s), and once per block the ring weights 2m+1 = (2 m0 + 63) - 2b of the set bits b
+// are summed with masked popcounts: sum_b b = sum_k 2^k popc(bits & M_k).
+template <typename Tz, int DIR>
+__device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
+                                              const typename Tab<Tz>::type *__restrict__ tab,
+                                              uint32_t &U) {
+    Tz mx = neg_inf<Tz>();
+    const int mfull = (mb == K) ? K - 1 : mb;
+    uint32_t base = 0;                                // sum over blocks of (2 m0 + 63) popc(bits)
+    uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;  // sum over blocks of popc(bits & M_k)
+    int m = 1;
+    for (; m + 31 <= mfull; m += 32) {
+        uint32_t bits = 0;
+#pragma unroll
+        for (int s = 0; s < 32; ++s) {
+            const Tz z = zp[DIR * (m + s)];
+            const Tz th = slope_div(sub_rn(z, h), tab[m + s]);
+            vis_step(th, mx, bits);
+        }
+        base += (uint32_t)(2 * m + 63) * (uint32_t)__popc(bits);
+        q0 += __popc(bits & 0xAAAAAAAAu);
+        q1 += __popc(bits & 0xCCCCCCCCu);
+        q2 += __popc(bits & 0xF0F0F0F0u);
+        q3 += __popc(bits & 0xFF00FF00u);
+        q4 += __popc(bits & 0xFFFF0000u);
+    }
+    uint32_t acc = base - 2u * (q0 + 2u * q1 + 4u * q2 + 8u * q3 + 16u * q4);
+    for (; m <= mfull; ++m) {
+        const Tz z = zp[DIR * m];
+        const Tz th = slope_div(sub_rn(z, h), tab[m]);
+        const bool v = th > mx;
+        mx = v ? th : mx;
+        acc += v ? (uint32_t)(2 * m + 1) : 0u;
+    }
+    U += acc;
+    uint32_t e = 0;
+    if (mb == K && K >= 1) {
+        const Tz z = zp[DIR * K];
+        const Tz th = slope_div(sub_rn(z, h), tab[K]);
+        e = th > mx ? 1u : 0u;
+    }
+    return e;
+}
+
+template <typename Tz> __device__ __forceinline__ Tz h0_of(const ChunkArgs &a);
+template <> __device__ __forceinline__ float h0_of<float>(const ChunkArgs &a) { return a.h0f; }
+template <> __device__ __forceinline__ double h0_of<double>(const ChunkArgs &a) { return a.h0; }
+
+// Skewed row index for workgroup b of a sector with N rows: middle-out, so the long rows of
+// the parallelogram start first and the short corner rows fill the tail.
+__device__ __forceinline__ int row_of_block(int b, int N) {
+    const int c = (N - 1) >> 1;
+    return (b & 1) ? c + ((b + 1) >> 1) : c - (b >> 1);
+}
+
+// Load skewed row `ri` (existing samples jlo..jlo+nt-1) into LDS with TVS_SWEEP_PAD -inf
+// sentinels on both sides. Returns nt (0 for an empty row).
+template <typename Tz>
+__device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int ri, const Tz *skw, Tz *row,
+                                        int &jlo) {
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    const int t = s.t0 + ri;
+    jlo = row_first(s.T, t, Hx, Wx);
+    const int jhi = row_last(s.T, t, Hx, Wx);
+    const int nt = jhi - jlo + 1;
+    if (nt <= 0) return 0;
+    const Tz *src = skw + s.off + (int64_t)ri * a.pitch + jlo;
+    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
+        const int q = x - TVS_SWEEP_PAD;
+        row[x] = (q >= 0 && q < nt) ? src[q] : neg_inf<Tz>();
+    }
+    __syncthreads();
+    return nt;
+}
+
+template <typename Tz, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
+                                                   uint32_t *__restrict__ V,
+                                                   const typename Tab<Tz>::type *__restrict__ tab) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Tz *row = reinterpret_cast<Tz *>(lds_raw);
+    const SecDev &s = a.s[blockIdx.y];
+    if ((int)blockIdx.x >= s.nrows) return;
+    const int ri = row_of_block(blockIdx.x, s.nrows);
+    int jlo;
+    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
+    if (nt == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int K = s.K;
+    const Tz h0 = h0_of<Tz>(a);
+    const int nseg = (nt + 63) >> 6;
+    uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
+    for (int sg = wv; sg < nseg; sg += NW) {
+        const int q = (sg << 6) + lane;
+        const Tz *zp = row + TVS_SWEEP_PAD + q;
+        const Tz h = add_rn(zp[0], h0);
+        uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
+        uint32_t e = (K >= 1) ? 0u : 2u;
+        const int fwd = min(K, nt - 1 - (sg << 6));
+        const int bwd = min(K, min(nt - 1, (sg << 6) + 63));
+        e += sweep_dir<Tz, +1>(zp, h, fwd, K, tab, U);
+        e += sweep_dir<Tz, -1>(zp, h, bwd, K, tab, U);
+        if (q < nt) dst[q] = U | (e << 30);
+    }
+}
+
+// Comparison variant: one wavefront per POV and direction, lanes = 64 consecutive targets,
+// the running horizon is the exclusive wavefront prefix-max carried across 64-target chunks.
+template <typename Tz, int NW>
+__global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const Tz *__restrict__ skw,
+                                                        uint32_t *__restrict__ V,
+                                                        const typename Tab<Tz>::type *__restrict__ tab) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Tz *row = reinterpret_cast<Tz *>(lds_raw);
+    const SecDev &s = a.s[blockIdx.y];
+    if ((int)blockIdx.x >= s.nrows) return;
+    const int ri = row_of_block(blockIdx.x, s.nrows);
+    int jlo;
+    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
+    if (nt == 0) return;
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int K = s.K;
+    const Tz h0 = h0_of<Tz>(a);
+    uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
+    for (int q = wv; q < nt; q += NW) {
+        const Tz *zp = row + TVS_SWEEP_PAD + q;
+        const Tz h = add_rn(zp[0], h0);
+        uint32_t U = 0, e = 0;
+        for (int dir = 1; dir >= -1; dir -= 2) {
+            const int M = min(K, dir > 0 ? nt - 1 - q : q);  // targets in range
+            Tz carry = neg_inf<Tz>();
+            for (int m0 = 0; m0 < M; m0 += 64) {
+                const int m = m0 + lane + 1;
+                const bool ok = m <= M;
+                const Tz th = ok ? slope_div(sub_rn(zp[dir * m], h), tab[m]) : neg_inf<Tz>();
+                const Tz incl = wave_prefix_max(th);
+                const Tz excl = vmax(carry, wave_shift_up(neg_inf<Tz>(), incl));
+                if (ok && th > excl) {
+                    if (m < K) U += (uint32_t)(2 * m + 1);
+                    else e += 1;
+                }
+                carry = vmax(carry, lane63(incl));
+            }
+        }
+        U = wave_sum_u32(U);
+        e = wave_sum_u32(e);
+        if (lane == 0) {
+            if (K >= 1) U += 2u; else e += 2u;
+            dst[q] = U | (e << 30);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------- back-projection
+
+__device__ __forceinline__ double ring_sum(uint32_t v, double clip) {
+    return (double)(v & 0x3fffffffu) + (double)(v >> 30) * clip;
+}
+
+// Each thread owns one DEM cell and walks the chunk's sectors in order: VX = (1-r) V(p-d) +
+// r V(p-d-1) in the sector's base frame, times the sector's ring area; double accumulation
+// (or float Kahan when kahan_sum is given, the running sum and compensation kept in HBM
+// between chunks). `first` starts from zero, `last` writes the double result.
+__global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint32_t *__restrict__ V,
+                                                  double *__restrict__ out, float *__restrict__ ksum,
+                                                  float *__restrict__ kc, int first, int last) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    const int64_t cell = (int64_t)i * a.W + j;
+    if (ksum == nullptr) {
+        double acc = first ? 0.0 : out[cell];
+        for (int k = 0; k < a.nsec; ++k) {
+            const SecDev &s = a.s[k];
+            int p, q;
+            to_frame(s.kase, a.W, i, j, p, q);
+            int d;
+            double r;
+            col_offset(s.T, q, d, r);
+            const uint32_t *col = V + s.off + q;
+            const int ri = p - d - s.t0;
+            const double A = ring_sum(col[(int64_t)ri * a.pitch], s.clip);
+            double vx = A;
+            if (r != 0.0) {
+                const double B = ring_sum(col[(int64_t)(ri - 1) * a.pitch], s.clip);
+                vx = (1.0 - r) * A + r * B;
+            }
+            acc += s.scale * vx;
+        }
+        out[cell] = acc;
+    } else {
+        float sum = first ? 0.0f : ksum[cell];
+        float c = first ? 0.0f : kc[cell];
+        for (int k = 0; k < a.nsec; ++k) {
+            const SecDev &s = a.s[k];
+            int p, q;
+            to_frame(s.kase, a.W, i, j, p, q);
+            int d;
+            double r;
+            col_offset(s.T, q, d, r);
+            const uint32_t *col = V + s.off + q;
+            const int ri = p - d - s.t0;
+            const float A = (float)ring_sum(col[(int64_t)ri * a.pitch], s.clip);
+            float vx = A;
+            if (r != 0.0) {
+                const float B = (float)ring_sum(col[(int64_t)(ri - 1) * a.pitch], s.clip);
+                const float rf = (float)r;
+                vx = __fadd_rn(__fmul_rn(1.0f - rf, A), __fmul_rn(rf, B));
+            }
+            const float term = __fmul_rn((float)s.scale, vx);
+            const float y = __fsub_rn(term, c);
+            const float t = __fadd_rn(sum, y);
+            c = __fsub_rn(__fsub_rn(t, sum), y);
+            sum = t;
+        }
+        if (last) out[cell] = (double)sum - (double)c;
+        else { ksum[cell] = sum; kc[cell] = c; }
+    }
+}
+
+// ------------------------------------------------------------------------------ singular
+// One wavefront per line of sight (2 per sector), lanes = 64 consecutive targets. Targets
+// lie on the straight line through the POV: offset d_j - d_q0 rows plus fraction r_j - r_q0
+// (renormalised into [0,1) and snapped like Alg. 6's weights). A target is visible iff its
+// slope beats the maximum over all earlier targets: the exclusive wavefront prefix-max of the
+// chunk, combined with the maximum carried from earlier chunks.
+template <typename Tz>
+__global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float *__restrict__ dem,
+                                                  uint32_t *__restrict__ rayV) {
+    const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ray >= 2 * a.nsec) return;
+    const int lane = threadIdx.x & 63;
+    const SecDev &s = a.s[ray >> 1];
+    const int dir = (ray & 1) ? -1 : 1;
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    int p0, q0;
+    to_frame(s.kase, a.W, a.pov_i, a.pov_j, p0, q0);
+    int d0;
+    double r0;
+    col_offset(s.T, q0, d0, r0);
+    const float zpov = dem[frame_index(s.kase, a.W, p0, q0)];
+    const Tz h = add_rn((Tz)zpov, h0_of<Tz>(a));
+    const int K = s.K;
+    Tz carry = neg_inf<Tz>();
+    uint32_t U = 0, e = 0;
+    for (int m0 = 0;; m0 += 64) {
+        const int m = m0 + lane + 1;
+        const int j = q0 + dir * m;
+        bool ok = j >= 0 && j < Wx && m <= K;
+        Tz th = neg_inf<Tz>();
+        if (ok) {
+            int dj;
+            double rj;
+            col_offset(s.T, j, dj, rj);
+            int dd = dj - d0;
+            double dr = rj - r0;
+            if (dr < 0.0) {
+                dd -= 1;
+                dr = __dadd_rn(dr, 1.0);
+            }
+            if (dr < 1e-9) {
+                dr = 0.0;
+            } else if (dr > 1.0 - 1e-9) {
+                dd += 1;
+                dr = 0.0;
+            }
+            const int u = p0 + dd;
+            ok = sample_exists(u, dr, Hx);
+            if (ok) {
+                const double z64 =
+                    interp(u, dr, Hx, [&](int v) { return dem[frame_index(s.kase, a.W, v, j)]; });
+                const Tz z = (Tz)z64;
+                const Tz dz = sub_rn(z, h);
+                if constexpr (sizeof(Tz) == 4) th = __fdiv_rn(dz, (float)m);
+                else th = __ddiv_rn(dz, (double)m);
+            }
+        }
+        // existence is monotone along the line of sight, so the valid lanes form a prefix
+        const Tz incl = wave_prefix_max(th);
+        const Tz excl = vmax(carry, wave_shift_up(neg_inf<Tz>(), incl));
+        if (ok && th > excl) {
+            if (m < K) U += (uint32_t)(2 * m + 1);
+            else e += 1;
+        }
+        carry = vmax(carry, lane63(incl));
+        if (!__all(ok)) break;
+    }
+    U = wave_sum_u32(U);
+    e = wave_sum_u32(e);
+    if (lane == 0) {
+        if (K >= 1) U += 1u; else e += 1u;  // the POV's own ring
+        rayV[2 * a.k_base + ray] = U | (e << 30);
+    }
+}
+
+__global__ void k_singular_sum(const ChunkArgs a, const uint32_t *__restrict__ rayV, double *area, int first) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double acc = first ? 0.0 : *area;
+    for (int k = 0; k < a.nsec; ++k) {
+        const SecDev &s = a.s[k];
+        const uint32_t f = rayV[2 * (a.k_base + k)];
+        const uint32_t b = rayV[2 * (a.k_base + k) + 1];
+        const double cv = ring_sum(f, s.clip) + ring_sum(b, s.clip);
+        acc += s.scale * cv;
+    }
+    *area = acc;
+}
+
+// ------------------------------------------------------------------------------ launchers
+
+constexpr int SWEEP_WAVES = 4;
+
+size_t sweep_lds_bytes(int maxWx, bool f64) {
+    return (size_t)(maxWx + 2 * TVS_SWEEP_PAD) * (f64 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st) {
+    k_divtab<<<(n + 255) / 256, 256, 0, st>>>(tab32, tab64, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
+    const int64_t blocks = (n + 255) / 256;
+    k_fill_u32<<<(unsigned)(blocks < 65536 ? (blocks > 0 ? blocks : 1) : 65536), 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw, bool f64,
+                           hipStream_t st) {
+    dim3 grid((maxWx + RL_TW - 1) / RL_TW, (maxRows + RL_TH - 1) / RL_TH, a.nsec);
+    if (f64) k_relocate<double><<<grid, 256, 0, st>>>(a, dem, (double *)skw);
+    else k_relocate<float><<<grid, 256, 0, st>>>(a, dem, (float *)skw);
+    return hipGetLastError();
+}
+
+template <typename F>
+static hipError_t set_lds(F f, size_t bytes) {
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)bytes);
+}
+
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
+                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, hipStream_t st) {
+    dim3 grid(maxRows, a.nsec);
+    const size_t lds = sweep_lds_bytes(maxWx, f64);
+    hipError_t e;
+    if (f64) {
+        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES> : k_sweep<double, SWEEP_WAVES>;
+        if ((e = set_lds(f, lds)) != hipSuccess) return e;
+        f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const double *)skw, V, tab64);
+    } else {
+        auto f = scan ? k_sweep_scan<float, SWEEP_WAVES> : k_sweep<float, SWEEP_WAVES>;
+        if ((e = set_lds(f, lds)) != hipSuccess) return e;
+        f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const float *)skw, V, tab32);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum, float *kahan_c,
+                           int first, int last, hipStream_t st) {
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4);
+    k_backproj<<<grid, 256, 0, st>>>(a, V, out, kahan_sum, kahan_c, first, last);
+    return hipGetLastError();
+}
+
+hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, hipStream_t st) {
+    const int blocks = (2 * a.nsec + 3) / 4;
+    if (f64) k_singular<double><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    else k_singular<float><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    return hipGetLastError();
+}
+
+hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first, hipStream_t st) {
+    k_singular_sum<<<1, 64, 0, st>>>(a, rayV, area, first);
+    return hipGetLastError();
+}
+
+}  // namespace tvs

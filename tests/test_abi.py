@@ -1,0 +1,94 @@
+"""C-ABI checks that need no GPU: the library loads, exports every declared entry point, rejects
+bad arguments before touching a device, and its host-side sector plan matches the oracle's."""
+import ctypes as C
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "libtvs.h")
+
+
+@pytest.fixture(scope="module")
+def tvs():
+    import paper_2003_02200_amd as t
+
+    if not os.path.exists(t.SO_PATH):
+        from paper_2003_02200_amd.build import build
+
+        build()
+    t.lib()
+    return t
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(tvs_\w+)\s*\(", text, re.M)))
+
+
+def test_exports_every_declared_symbol(tvs):
+    names = _declared()
+    assert len(names) >= 11
+    L = C.CDLL(tvs.SO_PATH)
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_abi_version(tvs):
+    m = re.search(r"#define TVS_ABI_VERSION (\d+)", open(HEADER).read())
+    assert tvs.abi_version() == int(m.group(1))
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(spacing=0.0), -1), (dict(spacing=math.nan), -1), (dict(spacing=math.inf), -1),
+    (dict(obs_height=math.nan), -1), (dict(n_sectors=0), -1), (dict(n_sectors=40000), -1),
+    (dict(max_dist=0.0), -1), (dict(max_dist=-5.0), -1), (dict(max_dist=math.nan), -1),
+])
+def test_rejects_bad_scalars(tvs, kw, status):
+    args = dict(spacing=10.0, obs_height=1.5, n_sectors=8, max_dist=math.inf)
+    args.update(kw)
+    with pytest.raises(tvs.TvsError) as ei:
+        tvs.total_viewshed(np.zeros((4, 4), np.float32), **args)
+    assert ei.value.status == status
+
+
+def test_rejects_bad_grid(tvs):
+    L = tvs.lib()
+    out = np.zeros(4, np.float64)
+    d = np.zeros(4, np.float32)
+    vp = C.c_void_p
+    assert L.tvs_total_viewshed(None, 2, 2, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp)) == -1
+    assert L.tvs_total_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, None) == -1
+    assert L.tvs_total_viewshed(d.ctypes.data_as(vp), 0, 2, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp)) == -1
+    assert L.tvs_total_viewshed(d.ctypes.data_as(vp), 40000, 2, 10.0, 1.5, 4, math.inf,
+                                out.ctypes.data_as(vp)) == -4
+    assert L.tvs_total_viewshed_async(None, 2, 2, 10.0, 1.5, 4, math.inf, None, None) == -1
+    bad = np.zeros((3, 3), np.float32)
+    bad[2, 1] = np.inf
+    with pytest.raises(tvs.TvsError) as ei:
+        tvs.total_viewshed(bad, 10.0, 1.5, 4)
+    assert ei.value.status == -1 and "(2, 1)" in str(ei.value)
+    area = C.c_double(7.0)
+    assert L.tvs_singular_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, 2, 0, C.byref(area),
+                                   None) == -1
+    mask = np.zeros(4, np.uint8)
+    assert L.tvs_singular_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, 0, 0, C.byref(area),
+                                   mask.ctypes.data_as(vp)) == -1
+    assert area.value == 7.0  # outputs untouched on error
+    assert b"mask" in L.tvs_last_error()
+
+
+@pytest.mark.parametrize("H,W,n,R", [(37, 53, 7, math.inf), (1, 1, 3, 5.0), (64, 17, 180, 300.0),
+                                     (5, 200, 13, 77.7), (2000, 2000, 180, 10000.0), (128, 128, 180, 1280.0)])
+def test_plan_matches_oracle(tvs, orc, H, W, n, R):
+    """Skewed-grid shapes and the closed-form work count agree with the oracle's independent plan."""
+    for k in range(0, n, max(1, n // 12)):
+        o = orc.sector_info(H, W, 10.0, n, R, k)
+        assert tvs.sector_shape(H, W, n, k) == (o["nrows"], o["Wx"], o["t0"])
+    if H * W <= 5000 or (H, W) == (128, 128):
+        assert tvs.los_evals(H, W, 10.0, n, R) == orc.los_evals(H, W, 10.0, n, R)
+    if (H, W) == (2000, 2000):
+        assert tvs.los_evals(H, W, 10.0, n, R) == (920007832528, 720351824)

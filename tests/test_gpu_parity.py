@@ -1,0 +1,251 @@
+"""GPU parity of libtvs against the CPU oracle (run on an MI355X; marked `gpu`).
+
+Bar (from the method's arithmetic):
+* per-sector skewed viewshed (integer ring sums U and clipped-ring counts e): bit-exact against
+  the oracle taking the same decisions in the same precision -- float for the default path
+  (the paper's single-precision kernels), double for TVS_FLAG_SLOPE_F64;
+* total viewshed map: equal to that oracle up to double summation order (rtol 1e-12);
+* against the all-double oracle: per-cell relative error <= 1e-4 on cells without a horizon
+  flip, horizon flips (POV-sector pairs whose U or e differ) <= 1e-5 of all pairs.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import cone, flat, fractal_dem, plane, workload_dem, WORKLOADS
+
+pytestmark = pytest.mark.gpu
+INF = math.inf
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tvs():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2003_02200_amd as t
+
+    t.lib()  # raises if the HIP library is missing: no fallback
+    return t
+
+
+def packed(o):
+    v = o["U"].astype(np.uint32) | (o["e"].astype(np.uint32) << np.uint32(30))
+    v[o["valid"] == 0] = np.uint32(0xFFFFFFFF)
+    return v
+
+
+def _int_dem(H, W, seed, hi=12):
+    rng = np.random.default_rng(seed)
+    return np.round(rng.uniform(0, hi, (H, W))).astype(np.float32)
+
+
+SHAPES = [
+    # (H, W, n, R, terrain)
+    (1, 1, 3, INF, "fractal"),
+    (1, 9, 4, INF, "int"),
+    (9, 1, 4, 25.0, "int"),
+    (2, 2, 8, INF, "fractal"),
+    (37, 53, 7, INF, "fractal"),
+    (37, 53, 7, 123.4, "int"),
+    (53, 37, 12, 530.0, "fractal"),
+    (70, 130, 3, 5.0, "fractal"),      # rho < 1: no target in range
+    (64, 64, 2, INF, "flat"),
+    (17, 300, 8, INF, "fractal"),      # long rows: many segments and 32-step blocks
+    (300, 17, 9, 2000.0, "int"),
+    (130, 70, 180, 700.0, "fractal"),
+    (45, 45, 4, 300.0, "plane"),
+]
+
+
+def _dem(H, W, kind, seed=3):
+    if kind == "fractal":
+        return fractal_dem(max(H, W), seed, 0.6, 400.0)[:H, :W].copy()
+    if kind == "int":
+        return _int_dem(H, W, seed)
+    if kind == "flat":
+        return flat(H, W, 17.0)
+    return plane(H, W, 0.75, -0.5, 300.0)
+
+
+def _sectors(n):
+    return list(range(n)) if n <= 16 else sorted(set(list(range(0, n, 7)) + [n // 4, n // 2, 3 * n // 4, n - 1]))
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
+def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
+    dem = _dem(H, W, kind)
+    for k in _sectors(n):
+        note(f"sector_rays float H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=32)
+        assert g.shape == o["U"].shape
+        bad = np.argwhere(g != packed(o))
+        assert bad.size == 0, f"k={k}: {len(bad)} samples differ, first {bad[:3].tolist()}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
+def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
+    dem = _dem(H, W, kind, seed=5)
+    for k in _sectors(n):
+        note(f"sector_rays double H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_F64)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=64)
+        assert np.array_equal(g, packed(o)), f"k={k}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[1::3])
+def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
+    """The lane-per-target sweep (wavefront prefix-max horizon) gives the same integers."""
+    dem = _dem(H, W, kind, seed=8)
+    for k in _sectors(n)[:6]:
+        note(f"sector_rays scan H={H} W={W} n={n} R={R} k={k}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=32)
+        assert np.array_equal(g, packed(o)), f"k={k}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
+def test_total_small(tvs, orc, H, W, n, R, kind):
+    dem = _dem(H, W, kind, seed=11)
+    note(f"total H={H} W={W} n={n} R={R} kind={kind}")
+    g = tvs.total_viewshed(dem, 10.0, 1.5, n, R)
+    o32 = orc.total(dem, 10.0, 1.5, n, R, prec=32)
+    np.testing.assert_allclose(g, o32, rtol=1e-12, atol=0)
+    note(f"total f64 H={H} W={W} n={n} R={R} kind={kind}")
+    g64 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_F64)
+    o64 = orc.total(dem, 10.0, 1.5, n, R, prec=64)
+    np.testing.assert_allclose(g64, o64, rtol=1e-12, atol=0)
+
+
+def test_flat_full_disc_on_gpu(tvs):
+    """P1 through the GPU: interior cells of flat ground get pi R^2."""
+    H = W = 90
+    R = 300.0
+    note("flat full disc 90x90 n=45")
+    g = tvs.total_viewshed(flat(H, W, 5.0), 10.0, 1.5, 45, R)
+    m = int(math.ceil(R / 10.0)) + 2
+    np.testing.assert_allclose(g[m:-m, m:-m], math.pi * R * R, rtol=1e-12)
+    assert np.all(g <= math.pi * R * R * (1 + 1e-12))
+
+
+def test_kahan_float_accumulation(tvs, orc):
+    dem = fractal_dem(64, 21, 0.6, 900.0)
+    note("kahan32 64x64 n=60")
+    g = tvs.total_viewshed(dem, 10.0, 1.5, 60, 500.0, flags=tvs.FLAG_ACC_KAHAN32)
+    o = orc.total(dem, 10.0, 1.5, 60, 500.0, prec=32)
+    np.testing.assert_allclose(g, o, rtol=2e-6)
+
+
+def test_async_torch_stream_and_stats(tvs):
+    import torch
+
+    dem = fractal_dem(96, 2, 0.6, 800.0)[:80].copy()
+    note("async on a side stream with stats 80x96 n=30")
+    host = tvs.total_viewshed(dem, 10.0, 1.5, 30, 400.0)
+    s = torch.cuda.Stream()
+    d = torch.from_numpy(dem).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out, st = tvs.total_viewshed(d, 10.0, 1.5, 30, 400.0, stream=s, stats=True)
+    s.synchronize()
+    np.testing.assert_array_equal(out.cpu().numpy(), host)
+    ev, pairs = tvs.los_evals(80, 96, 10.0, 30, 400.0)
+    assert st.los_evals == ev and st.pov_sector_pairs == pairs
+    assert st.sweep_launches == st.chunks and st.sweep_ms > 0
+
+
+@pytest.mark.parametrize("H,W,n,R,pov", [(37, 53, 7, INF, (5, 9)), (64, 64, 180, 500.0, (0, 0)),
+                                         (64, 64, 180, 500.0, (63, 17)), (1, 1, 3, INF, (0, 0)),
+                                         (200, 90, 24, 1500.0, (100, 45)), (50, 50, 4, INF, (10, 40))])
+def test_singular(tvs, orc, H, W, n, R, pov):
+    dem = fractal_dem(max(H, W), 17, 0.6, 600.0)[:H, :W].copy()
+    i0, j0 = pov
+    note(f"singular H={H} W={W} n={n} R={R} pov={pov}")
+    area, rays = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, rays=True)
+    o = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=32)
+    want = o["U"].astype(np.uint32) | (o["e"].astype(np.uint32) << np.uint32(30))
+    assert np.array_equal(rays, want)
+    assert area == pytest.approx(o["area"], rel=1e-12)
+    area64 = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, flags=tvs.FLAG_SLOPE_F64)
+    o64 = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=64)
+    assert area64 == pytest.approx(o64["area"], rel=1e-12)
+
+
+def test_singular_cone_shadow(tvs):
+    """P12 through the GPU ray scan: the 45 deg line of sight to a cone apex 50 cells away."""
+    dem = cone(81, 81, 60, 60, 30.0, 8.0)
+    note("singular cone")
+    _, rays = tvs.singular_viewshed(dem, 10.0, 1.5, 4, INF, 10, 10, rays=True)
+    assert rays[2] == 51 ** 2
+
+
+def _flip_stats(tvs, orc, dem, dx, h0, n, R, sectors):
+    flips = pairs = 0
+    for k in sectors:
+        g = tvs.debug_sector_rays(dem, dx, h0, n, R, k)
+        o = orc.sector_V(dem, dx, h0, n, R, k, prec=64)
+        p = packed(o)
+        v = o["valid"].astype(bool)
+        assert np.array_equal(g == 0xFFFFFFFF, ~v)
+        pairs += int(v.sum())
+        flips += int(np.sum(g[v] != p[v]))
+    return flips, pairs
+
+
+def test_workload_128_full_map(tvs, orc):
+    """The 128 x 128, 180-sector workload: whole map against both oracle precisions."""
+    w = WORKLOADS["tvs128"]
+    dem = workload_dem("tvs128")
+    args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    note("workload tvs128 total")
+    g = tvs.total_viewshed(dem, *args)
+    o32 = orc.total(dem, *args, prec=32)
+    np.testing.assert_allclose(g, o32, rtol=1e-12)
+    o64 = orc.total(dem, *args, prec=64)
+    note("workload tvs128 flips")
+    flips, pairs = _flip_stats(tvs, orc, dem, *args, range(w["n_sectors"]))
+    rel = np.abs(g - o64) / o64
+    print(f"tvs128: pairs={pairs} flips={flips} rate={flips / pairs:.3g} max_rel={rel.max():.3g} "
+          f"cells>1e-4={int((rel > 1e-4).sum())}", flush=True)
+    assert flips / pairs <= 1e-5
+    # cells off by more than rounding are exactly the cells fed by a flipped pair: at most 2 per flip
+    assert int((rel > 1e-10).sum()) <= 2 * flips
+    assert np.median(rel) < 1e-12
+
+
+def test_workload_2000_sampled(tvs, orc):
+    """The 2000 x 2000, 180-sector, 10 km workload in the bench's launch configuration: sampled
+    cells against the oracle cell by cell, plus properties that hold at any size."""
+    import torch
+
+    w = WORKLOADS["tvs2000"]
+    dem = workload_dem("tvs2000")
+    args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    note("workload tvs2000 total (device-resident, async)")
+    d = torch.from_numpy(dem).cuda()
+    out = tvs.total_viewshed(d, *args)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    R = w["max_dist"]
+    assert np.all(np.isfinite(g)) and np.all(g > 0) and np.all(g <= math.pi * R * R * (1 + 1e-12))
+    rng = np.random.default_rng(2000)
+    cells = [(0, 0), (0, 1999), (1999, 0), (1999, 1999), (1000, 1000), (999, 3), (3, 1500)]
+    cells += [tuple(int(x) for x in rng.integers(0, 2000, 2)) for _ in range(25)]
+    worst32 = 0.0
+    worst64 = 0.0
+    for (i, j) in cells:
+        o32 = orc.total(dem, *args, prec=32, window=(i, j, 1, 1))[0, 0]
+        o64 = orc.total(dem, *args, prec=64, window=(i, j, 1, 1))[0, 0]
+        worst32 = max(worst32, abs(g[i, j] - o32) / o32)
+        worst64 = max(worst64, abs(g[i, j] - o64) / o64)
+    print(f"tvs2000 sampled cells={len(cells)} max_rel_vs_f32={worst32:.3g} max_rel_vs_f64={worst64:.3g}", flush=True)
+    assert worst32 <= 1e-12
+    assert worst64 <= 1e-2
