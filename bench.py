@@ -20,11 +20,13 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs x 4 SIMD16 = 64 FP32 lanes per CU per clock, 2.4 GHz peak engine clock,
-# non-packed VALU issue (packed FP32 is not used). One line-of-sight evaluation is 5 algorithmic
-# operations: subtract, divide, compare, max, conditional integer add.
-CU, LANES, CLOCK_HZ = 256, 64, 2.4e9
-ALU_PEAK_OPS = CU * LANES * CLOCK_HZ          # 3.93e13 lane-ops/s
+# MI355X: 256 CUs at a 2.4 GHz peak engine clock; the published FP32 vector peak, 157.3 TFLOP/s,
+# is 128 FP32 lane-operations per CU per clock with an FMA counted as 2 flops. Plain (non-packed)
+# FP32 VALU instructions reach that issue rate on gfx950 (VALU counters of the sweep show more
+# than 64 lanes/clk/CU). One line-of-sight evaluation is 5 algorithmic operations: subtract,
+# divide, compare, max, conditional integer add; the peak counts each lane-operation once.
+CU, LANES, CLOCK_HZ = 256, 128, 2.4e9
+ALU_PEAK_OPS = CU * LANES * CLOCK_HZ          # 7.86e13 lane-ops/s = 157.3 TFLOP/s / 2
 OPS_PER_EVAL = 5
 HBM_PEAK_GBS = 8000.0
 

@@ -8,10 +8,11 @@
  * ---------------------------------------
  * dem        Row-major, C-contiguous rows x cols float32 elevations in metres. Row index
  *            grows "south", column index "east". Cells are square, `spacing` metres apart.
- *            Every elevation must be finite (the paper has no no-data concept).
+ *            Every elevation must be finite (the paper has no no-data concept) and either 0 or
+ *            at least 2^-60 m in magnitude (the sweep's sign tests assume no slope underflows).
  * spacing    Grid step in metres, finite and > 0.
  * obs_height Height of the observer above the ground at the point of view (POV), metres,
- *            finite. Targets are at ground level.
+ *            finite, 0 or at least 2^-60 in magnitude. Targets are at ground level.
  * n_sectors  Number of sector axes over 180 degrees, 1 <= n <= 32768. Axis k points at
  *            a_k = k*pi/n from +column toward +row; each axis carries a forward and a
  *            backward line of sight (a_k and a_k + 180 deg), each the axis of a
@@ -59,6 +60,9 @@ enum tvs_status {
 #define TVS_FLAG_SLOPE_F64 0x1u   /* visibility decided in double from double elevations */
 #define TVS_FLAG_SWEEP_SCAN 0x2u  /* sweep with one lane per target and wavefront prefix-max */
 #define TVS_FLAG_ACC_KAHAN32 0x4u /* float Kahan-compensated per-cell accumulation */
+#define TVS_FLAG_SLOPE_RCP 0x8u   /* float slope as the difference times the float reciprocal of
+                                     the distance (one product instead of an exactly rounded
+                                     quotient; float sweep only) */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for
@@ -100,7 +104,7 @@ int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double s
 
 /* Device-resident, stream-ordered total viewshed: d_dem and d_out are device pointers
  * (rows*cols float / double). Elevations are not inspected on the host: the caller
- * guarantees they are finite. */
+ * guarantees they are finite and 0 or at least 2^-60 m in magnitude. */
 int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
                              double obs_height, int32_t n_sectors, double max_dist,
                              double *d_out, void *hip_stream);

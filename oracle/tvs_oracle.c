@@ -48,7 +48,10 @@
  * Precision: prec = 64 takes every step in double. prec = 32 takes the visibility
  * decision the way the paper's single-precision kernels do (Alg. 7/8 declare float):
  * the interpolated elevation rounded to float, h = z + h0 in float, the slope as a
- * float division, compared in float. Ring sums and areas stay in double.
+ * float division, compared in float. Ring sums and areas stay in double. prec = 33 is the
+ * same float decision with the slope formed as the float difference times the float
+ * reciprocal of m -- not the paper's arithmetic but that of the GPU's reciprocal-product
+ * variant, kept here so that variant can be checked bit for bit.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math).
  */
@@ -258,7 +261,9 @@ static ray_t walk(const float *D, const sector_t *S, int mode, long long t_or_p0
         } else {
             float z32 = (float)z;
             float dz = z32 - h32;
-            float th = dz / (float)m;
+            float th;
+            if (prec == 32) th = dz / (float)m;
+            else th = dz * (1.0f / (float)m);  /* prec 33: the reciprocal-product variant */
             visible = th > mx32;
             if (visible) mx32 = th;
             th_rec = (double)th;
@@ -375,7 +380,7 @@ int oracle_sector_V(const float *dem, int rows, int cols, double dx, double h0, 
 {
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (k < 0 || k >= n || (prec != 32 && prec != 64)) return ORC_EINVAL;
+    if (k < 0 || k >= n || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
     sector_t S;
     memset(&S, 0, sizeof(S));
     if (sector_init(&S, k, n, rows, cols, dx, R) != ORC_OK) { sector_free(&S); return ORC_ENOMEM; }
@@ -412,7 +417,7 @@ int oracle_total(const float *dem, int rows, int cols, double dx, double h0, int
     long long evals = 0;
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (!out || (prec != 32 && prec != 64)) return ORC_EINVAL;
+    if (!out || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
     if (r0 < 0 || c0 < 0 || nr < 0 || nc < 0 || r0 + nr > rows || c0 + nc > cols) return ORC_EINVAL;
     sector_t *S = make_sectors(rows, cols, dx, n, R);
     if (!S) return ORC_ENOMEM;
@@ -467,7 +472,7 @@ int oracle_singular(const float *dem, int rows, int cols, double dx, double h0, 
 {
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (!out_area || (prec != 32 && prec != 64)) return ORC_EINVAL;
+    if (!out_area || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
     if (i0 < 0 || i0 >= rows || j0 < 0 || j0 >= cols) return ORC_EINVAL;
     sector_t *S = make_sectors(rows, cols, dx, n, R);
     if (!S) return ORC_ENOMEM;

@@ -89,12 +89,19 @@ Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
     return s;
 }
 
+// Elevations and the observer height must be finite, and either 0 or at least 2^-60 m in
+// magnitude. The second rule keeps every quantity of the sweep a multiple of 2^-83, so no slope
+// underflows to a signed zero (the kernels read strict comparisons from sign bits).
+const double TVS_MIN_MAGNITUDE = 0x1p-60;
+
+bool magnitude_ok(double v) { return v == 0.0 || fabs(v) >= TVS_MIN_MAGNITUDE; }
+
 int check_scalars(int rows, int cols, double dx, double h0, int n, double R) {
     if (rows < 1 || cols < 1) return fail(TVS_EINVAL, "rows and cols must be >= 1 (got %d x %d)", rows, cols);
     if (rows > TVS_MAX_SIDE || cols > TVS_MAX_SIDE)
         return fail(TVS_ERANGE, "grid %d x %d exceeds the %d-cell side limit", rows, cols, TVS_MAX_SIDE);
     if (!(dx > 0.0) || !isfinite(dx)) return fail(TVS_EINVAL, "spacing must be finite and > 0");
-    if (!isfinite(h0)) return fail(TVS_EINVAL, "obs_height must be finite");
+    if (!isfinite(h0) || !magnitude_ok(h0)) return fail(TVS_EINVAL, "obs_height must be finite, and 0 or >= 2^-60 m");
     if (n < 1 || n > TVS_MAX_SECTORS) return fail(TVS_EINVAL, "n_sectors must be in [1, %d]", TVS_MAX_SECTORS);
     if (isnan(R) || !(R > 0.0)) return fail(TVS_EINVAL, "max_dist must be > 0 (INFINITY allowed)");
     return TVS_OK;
@@ -103,9 +110,18 @@ int check_scalars(int rows, int cols, double dx, double h0, int n, double R) {
 int check_host_dem(const float *dem, int rows, int cols) {
     const int64_t N = (int64_t)rows * cols;
     for (int64_t x = 0; x < N; ++x)
-        if (!isfinite(dem[x]))
-            return fail(TVS_EINVAL, "non-finite elevation at cell (%lld, %lld)", (long long)(x / cols),
-                        (long long)(x % cols));
+        if (!isfinite(dem[x]) || !magnitude_ok(dem[x]))
+            return fail(TVS_EINVAL, "elevation %g at cell (%lld, %lld) is not finite, or is nonzero below 2^-60 m",
+                        (double)dem[x], (long long)(x / cols), (long long)(x % cols));
+    return TVS_OK;
+}
+
+int check_flags(uint32_t flags, bool accumulation) {
+    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_RCP |
+                           (accumulation ? TVS_FLAG_ACC_KAHAN32 : 0u);
+    if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
+    if ((flags & TVS_FLAG_SLOPE_RCP) && (flags & (TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN)))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_RCP applies to the float lane-per-POV sweep only");
     return TVS_OK;
 }
 
@@ -249,6 +265,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
+    const bool rcp = (flags & TVS_FLAG_SLOPE_RCP) != 0;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     pool_keep_memory(dev);
@@ -265,7 +282,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, scratch_budget());
     size_t maxChunk = 0;
     for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
-    const int tabN = std::max(H, W) + 1;
+    const int tabN = std::max(H, W);  // entries for m = 1 .. max(H, W)
     const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
     const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
     const size_t total = tabBytes + kahanBytes + 256 * 4 + maxChunk;
@@ -305,7 +322,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         HIPCHK(launch_relocate(a, c.maxWx, c.maxRows, d_dem, skw, f64, st));
         HIPCHK(tm.mark());
         HIPCHK(tm.begin(1));
-        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, st));
+        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, rcp, st));
         HIPCHK(tm.mark());
         if (d_debugV) {
             const Sector &s = S[0];
@@ -395,8 +412,7 @@ int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double
     if (!d_dem || !d_out) return fail(TVS_EINVAL, "null dem or out pointer");
     int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
     if (rc) return rc;
-    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_ACC_KAHAN32))
-        return fail(TVS_EINVAL, "unknown flags 0x%x", flags);
+    if (int rc2 = check_flags(flags, true)) return rc2;
     return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, flags, stats,
                      (hipStream_t)hip_stream, -1, nullptr, nullptr);
 }
@@ -500,7 +516,7 @@ int tvs_debug_sector_rays(const float *dem, int32_t rows, int32_t cols, double s
     int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
     if (rc) return rc;
     if (sector < 0 || sector >= n_sectors) return fail(TVS_EINVAL, "sector %d outside [0, %d)", sector, n_sectors);
-    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN)) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
+    if (int rc2 = check_flags(flags, false)) return rc2;
     if ((rc = check_host_dem(dem, rows, cols))) return rc;
     const Sector s = plan_sector(sector, n_sectors, rows, cols, spacing, max_dist);
     const size_t N = (size_t)rows * cols;

@@ -10,7 +10,8 @@
 // (48 x 48 B), so the library needs no host-to-device copy besides the caller's data.
 #define TVS_CHUNK 48
 // Sentinel columns on each side of a skewed row held in LDS by the sweep: a wavefront's 64
-// lines of sight all stop at the same step, lanes that run past their row end read these.
+// lines of sight all stop at the same step, so lanes whose row ends earlier (at most 63 steps
+// earlier) read these.
 #define TVS_SWEEP_PAD 64
 
 namespace tvs {
@@ -43,7 +44,7 @@ hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st);
 hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw,
                            bool f64, hipStream_t st);
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
-                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, hipStream_t st);
+                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, hipStream_t st);
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum,
                            float *kahan_c, int first, int last, hipStream_t st);
 hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, hipStream_t st);

@@ -46,6 +46,13 @@ __device__ __forceinline__ double slope_div(double d, double2 t) {
     double r = __fma_rn(-q, t.x, d);
     return __fma_rn(r, t.y, q);
 }
+// Variant slope: the float difference times the float reciprocal of m (one product; differs
+// from the correctly rounded quotient by at most one ulp).
+__device__ __forceinline__ float slope_rcp(float d, float2 t) { return __fmul_rn(d, t.y); }
+template <bool RCP> __device__ __forceinline__ float slope(float d, float2 t) {
+    return RCP ? slope_rcp(d, t) : slope_div(d, t);
+}
+template <bool RCP> __device__ __forceinline__ double slope(double d, double2 t) { return slope_div(d, t); }
 __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
@@ -147,13 +154,15 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
 
 // ------------------------------------------------------------------------ small kernels
 
+// Entry i holds {m, RN(1/m)} for m = i + 1, so that the 32-step blocks of the sweep, which
+// start at m = 1, 33, 65, ..., begin on 256-byte boundaries of the table.
 __global__ void k_divtab(float2 *tab32, double2 *tab64, int n) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    const float mf = (float)m;
-    const double md = (double)m;
-    tab32[m] = make_float2(mf, m ? __fdiv_rn(1.0f, mf) : 0.0f);
-    tab64[m] = make_double2(md, m ? __ddiv_rn(1.0, md) : 0.0);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float mf = (float)(i + 1);
+    const double md = (double)(i + 1);
+    tab32[i] = make_float2(mf, __fdiv_rn(1.0f, mf));
+    tab64[i] = make_double2(md, __ddiv_rn(1.0, md));
 }
 
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
@@ -196,19 +205,29 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
     const int ub = min(max(te + dhi + 1, 0), Hx - 1);
     const int nr = ub - ua + 1;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int ncol = jl - j0 + 1;
-    if (s.kase == 0 || s.kase == 3) {
+    // base-frame cell X[u][q] = dem[xb + u * xsu + q * xsq]
+    int64_t xb;
+    int xsu, xsq;
+    switch (s.kase) {
+    case 0: xb = 0; xsu = a.W; xsq = 1; break;
+    case 1: xb = 0; xsu = 1; xsq = a.W; break;
+    case 2: xb = a.W - 1; xsu = -1; xsq = a.W; break;
+    default: xb = a.W - 1; xsu = a.W; xsq = -1; break;
+    }
+    if (xsq == 1 || xsq == -1) {
         // base-frame rows are grid rows (reversed for case 3): coalesced along the row
         if (lane < ncol) {
-            for (int rr = wv; rr < nr; rr += 4)
-                tile[rr * RL_LP + lane] = dem[frame_index(s.kase, a.W, ua + rr, j0 + lane)];
+            const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + lane) * xsq;
+            for (int rr = wv; rr < nr; rr += 4) tile[rr * RL_LP + lane] = src[(int64_t)rr * xsu];
         }
     } else {
         // base-frame columns are grid rows: read along them and transpose into LDS
-        for (int c = wv; c < ncol; c += 4)
-            for (int rr = lane; rr < nr; rr += 64)
-                tile[rr * RL_LP + c] = dem[frame_index(s.kase, a.W, ua + rr, j0 + c)];
+        for (int c = wv; c < ncol; c += 4) {
+            const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + c) * xsq;
+            for (int rr = lane; rr < nr; rr += 64) tile[rr * RL_LP + c] = src[rr * xsu];
+        }
     }
     __syncthreads();
     if (lane >= ncol) return;
@@ -216,64 +235,78 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
     int d;
     double r;
     col_offset(s.T, q, d, r);
-    Tz *out = skw + s.off + q;
-    for (int rr = wv; rr <= te - tb; rr += 4) {
+    // existing rows of this column: u = t + d in [-1 (only if r > 0), Hx - 1]
+    const int tfirst = max(tb, (r != 0.0 ? -1 : 0) - d);
+    const int tlast = min(te, Hx - 1 - d);
+    int rr = wv + (((tfirst - tb - wv) + 3) >> 2 << 2);  // first rr >= tfirst - tb with rr = wv mod 4
+    if (rr < tfirst - tb) rr += 4;
+    const double w = __dsub_rn(1.0, r);
+    Tz *out = skw + s.off + (int64_t)(r0 + rr) * a.pitch + q;
+    const int64_t step = (int64_t)4 * a.pitch;
+    for (; rr <= tlast - tb; rr += 4, out += step) {
         const int u = tb + rr + d;
-        if (!sample_exists(u, r, Hx)) continue;
-        const double z = interp(u, r, Hx, [&](int v) { return tile[(v - ua) * RL_LP + lane]; });
-        out[(int64_t)(r0 + rr) * a.pitch] = (Tz)z;
+        const int uc = min(max(u, 0), Hx - 1);
+        const float av = tile[(uc - ua) * RL_LP + lane];
+        double z = (double)av;
+        if (r != 0.0 && u >= 0 && u < Hx - 1) {
+            const float bv = tile[(u + 1 - ua) * RL_LP + lane];
+            z = __dadd_rn(__dmul_rn(w, (double)av), __dmul_rn(r, (double)bv));
+        }
+        // + 0 turns a -0 elevation into +0 (no other value changes): the sweep's sign tests
+        // rely on slopes never being -0
+        *out = add_rn((Tz)z, (Tz)0);
     }
 }
 
 // -------------------------------------------------------------------------------- sweep
 
-// One direction of the lines of sight of a wavefront's 64 POVs. `zp` points at the lane's
-// POV in the LDS row, `mb` is the last step any lane of the wavefront needs (lanes whose
-// row ends earlier read -inf sentinels, which are never visible). Steps m < K add the whole
-// ring 2m+1 to U; the step m = K (the ring clipped at rho) is returned as 0/1.
-//
-// Steps run in blocks of 32: each step shifts its visibility bit into `bits` (step m0+s lands
-// in bit 31-s), and once per block the ring weights 2m+1 = (2 m0 + 63) - 2b of the set bits b
-// are summed with masked popcounts: sum_b b = sum_k 2^k popc(bits & M_k).
-template <typename Tz, int DIR>
-__device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
-                                              const typename Tab<Tz>::type *__restrict__ tab,
-                                              uint32_t &U) {
-    Tz mx = neg_inf<Tz>();
-    const int mfull = (mb == K) ? K - 1 : mb;
+// Ring sums of 32 visibility bits: step m0+s lands in bit 31-s, so the ring weight 2m+1 of set
+// bit b is (2 m0 + 63) - 2b, and sum_b b = sum_k 2^k popc(bits & M_k).
+struct RingAcc {
     uint32_t base = 0;                                // sum over blocks of (2 m0 + 63) popc(bits)
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;  // sum over blocks of popc(bits & M_k)
-    int m = 1;
-    for (; m + 31 <= mfull; m += 32) {
-        uint32_t bits = 0;
-#pragma unroll
-        for (int s = 0; s < 32; ++s) {
-            const Tz z = zp[DIR * (m + s)];
-            const Tz th = slope_div(sub_rn(z, h), tab[m + s]);
-            vis_step(th, mx, bits);
-        }
-        base += (uint32_t)(2 * m + 63) * (uint32_t)__popc(bits);
+    __device__ __forceinline__ void add(uint32_t bits, int m0) {
+        base += (uint32_t)(2 * m0 + 63) * (uint32_t)__popc(bits);
         q0 += __popc(bits & 0xAAAAAAAAu);
         q1 += __popc(bits & 0xCCCCCCCCu);
         q2 += __popc(bits & 0xF0F0F0F0u);
         q3 += __popc(bits & 0xFF00FF00u);
         q4 += __popc(bits & 0xFFFF0000u);
     }
-    uint32_t acc = base - 2u * (q0 + 2u * q1 + 4u * q2 + 8u * q3 + 16u * q4);
+    __device__ __forceinline__ uint32_t total() const {
+        return base - 2u * (q0 + 2u * q1 + 4u * q2 + 8u * q3 + 16u * q4);
+    }
+};
+
+// One direction of the lines of sight of a wavefront's 64 POVs. `zp` points at each lane's POV in
+// the LDS row; `mb` is the last step any lane of the wavefront needs (lanes whose row ends earlier
+// read -inf sentinels, which are never visible). Steps m < K add the whole ring 2m+1 to U; the
+// step m = K (the ring clipped at rho) is returned as 0/1. Steps run in blocks of 32 sharing one
+// scalar load of the {m, 1/m} table; each step is subtract, exactly rounded divide (3 VALU),
+// compare + add-with-carry into the bit mask, max.
+template <typename Tz, int DIR, bool RCP>
+__device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
+                                              const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U) {
+    Tz mx = neg_inf<Tz>();
+    const int mfull = (mb == K) ? K - 1 : mb;
+    RingAcc ra;
+    int m = 1;
+    for (; m + 31 <= mfull; m += 32) {
+        const auto *t = static_cast<const typename Tab<Tz>::type *>(__builtin_assume_aligned(tab + (m - 1), 256));
+        uint32_t bits = 0;
+#pragma unroll
+        for (int s = 0; s < 32; ++s) vis_step(slope<RCP>(sub_rn(zp[DIR * (m + s)], h), t[s]), mx, bits);
+        ra.add(bits, m);
+    }
+    uint32_t acc = ra.total();
     for (; m <= mfull; ++m) {
-        const Tz z = zp[DIR * m];
-        const Tz th = slope_div(sub_rn(z, h), tab[m]);
-        const bool v = th > mx;
-        mx = v ? th : mx;
-        acc += v ? (uint32_t)(2 * m + 1) : 0u;
+        const Tz th = slope<RCP>(sub_rn(zp[DIR * m], h), tab[m - 1]);
+        acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
+        mx = vmax(mx, th);
     }
     U += acc;
     uint32_t e = 0;
-    if (mb == K && K >= 1) {
-        const Tz z = zp[DIR * K];
-        const Tz th = slope_div(sub_rn(z, h), tab[K]);
-        e = th > mx ? 1u : 0u;
-    }
+    if (mb == K && K >= 1) e = slope<RCP>(sub_rn(zp[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
     return e;
 }
 
@@ -309,7 +342,7 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
     return nt;
 }
 
-template <typename Tz, int NW>
+template <typename Tz, int NW, bool RCP>
 __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
                                                    const typename Tab<Tz>::type *__restrict__ tab) {
@@ -322,7 +355,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
     const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
     if (nt == 0) return;
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int K = s.K;
     const Tz h0 = h0_of<Tz>(a);
     const int nseg = (nt + 63) >> 6;
@@ -335,8 +368,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
         uint32_t e = (K >= 1) ? 0u : 2u;
         const int fwd = min(K, nt - 1 - (sg << 6));
         const int bwd = min(K, min(nt - 1, (sg << 6) + 63));
-        e += sweep_dir<Tz, +1>(zp, h, fwd, K, tab, U);
-        e += sweep_dir<Tz, -1>(zp, h, bwd, K, tab, U);
+        e += sweep_dir<Tz, +1, RCP>(zp, h, fwd, K, tab, U);
+        e += sweep_dir<Tz, -1, RCP>(zp, h, bwd, K, tab, U);
         if (q < nt) dst[q] = U | (e << 30);
     }
 }
@@ -370,7 +403,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
             for (int m0 = 0; m0 < M; m0 += 64) {
                 const int m = m0 + lane + 1;
                 const bool ok = m <= M;
-                const Tz th = ok ? slope_div(sub_rn(zp[dir * m], h), tab[m]) : neg_inf<Tz>();
+                const Tz th = ok ? slope_div(sub_rn(zp[dir * m], h), tab[m - 1]) : neg_inf<Tz>();
                 const Tz incl = wave_prefix_max(th);
                 const Tz excl = vmax(carry, wave_shift_up(neg_inf<Tz>(), incl));
                 if (ok && th > excl) {
@@ -395,64 +428,120 @@ __device__ __forceinline__ double ring_sum(uint32_t v, double clip) {
     return (double)(v & 0x3fffffffu) + (double)(v >> 30) * clip;
 }
 
-// Each thread owns one DEM cell and walks the chunk's sectors in order: VX = (1-r) V(p-d) +
-// r V(p-d-1) in the sector's base frame, times the sector's ring area; double accumulation
-// (or float Kahan when kahan_sum is given, the running sum and compensation kept in HBM
-// between chunks). `first` starts from zero, `last` writes the double result.
+// A workgroup owns a 64 x 64 block of grid cells and walks the chunk's sectors in order. Per
+// sector the block maps to a 64 x 64 block of the sector's base frame; the skwVS rows its cells
+// blend, p - d_q - 1 .. p - d_q over the block, span at most 64 + 66 rows and are staged in LDS
+// by coalesced reads along skewed rows (pitch 65 words: the transposed cases read LDS down a
+// column). Each thread then forms VX = (1-r) V(p-d) + r V(p-d-1) for its 16 cells, times the
+// sector's ring area, and accumulates in double -- or in float with Kahan compensation, the
+// running sum and compensation kept in HBM between chunks. `first` starts from zero, `last`
+// writes the double result.
+constexpr int BP_T = 64;
+constexpr int BP_LP = BP_T + 1;
+constexpr int BP_MAXR = 2 * BP_T + 3;
+constexpr int BP_CELLS = BP_T * BP_T / 256;
+
+template <bool KAHAN>
 __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint32_t *__restrict__ V,
                                                   double *__restrict__ out, float *__restrict__ ksum,
                                                   float *__restrict__ kc, int first, int last) {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= a.H || j >= a.W) return;
-    const int64_t cell = (int64_t)i * a.W + j;
-    if (ksum == nullptr) {
-        double acc = first ? 0.0 : out[cell];
-        for (int k = 0; k < a.nsec; ++k) {
-            const SecDev &s = a.s[k];
-            int p, q;
-            to_frame(s.kase, a.W, i, j, p, q);
+    __shared__ uint32_t tile[BP_MAXR * BP_LP];
+    __shared__ int col_d[BP_T];
+    __shared__ double col_r[BP_T];
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int i0 = blockIdx.y * BP_T, j0 = blockIdx.x * BP_T;
+    const int j = j0 + lane;
+    double acc[BP_CELLS];
+    float fs[BP_CELLS], fc[BP_CELLS];
+#pragma unroll
+    for (int c = 0; c < BP_CELLS; ++c) {
+        const int i = i0 + wv + 4 * c;
+        const bool in = i < a.H && j < a.W;
+        const int64_t cell = (int64_t)i * a.W + j;
+        if (KAHAN) {
+            fs[c] = (first || !in) ? 0.0f : ksum[cell];
+            fc[c] = (first || !in) ? 0.0f : kc[cell];
+        } else {
+            acc[c] = (first || !in) ? 0.0 : out[cell];
+        }
+    }
+    const int ilast = min(i0 + BP_T, a.H) - 1, jlast = min(j0 + BP_T, a.W) - 1;
+    for (int k = 0; k < a.nsec; ++k) {
+        const SecDev &s = a.s[k];
+        // the block's base-frame rectangle [plo, phi] x [qlo, qhi]
+        int plo, phi, qlo, qhi;
+        switch (s.kase) {
+        case 0: plo = i0; phi = ilast; qlo = j0; qhi = jlast; break;
+        case 1: plo = j0; phi = jlast; qlo = i0; qhi = ilast; break;
+        case 2: plo = a.W - 1 - jlast; phi = a.W - 1 - j0; qlo = i0; qhi = ilast; break;
+        default: plo = i0; phi = ilast; qlo = a.W - 1 - jlast; qhi = a.W - 1 - j0; break;
+        }
+        int dlo, dhi;
+        double rtmp;
+        col_offset(s.T, qlo, dlo, rtmp);
+        col_offset(s.T, qhi, dhi, rtmp);
+        const int rbase = plo - dhi - s.t0 - 1;        // first skewed row needed
+        const int nr = (phi - dlo - s.t0) - rbase + 1;  // rows needed
+        const int nq = qhi - qlo + 1;
+        __syncthreads();  // the previous sector's tile is no longer read
+        if (threadIdx.x < nq) {
             int d;
             double r;
-            col_offset(s.T, q, d, r);
-            const uint32_t *col = V + s.off + q;
-            const int ri = p - d - s.t0;
-            const double A = ring_sum(col[(int64_t)ri * a.pitch], s.clip);
-            double vx = A;
-            if (r != 0.0) {
-                const double B = ring_sum(col[(int64_t)(ri - 1) * a.pitch], s.clip);
-                vx = (1.0 - r) * A + r * B;
-            }
-            acc += s.scale * vx;
+            col_offset(s.T, qlo + threadIdx.x, d, r);
+            col_d[threadIdx.x] = d;
+            col_r[threadIdx.x] = r;
         }
-        out[cell] = acc;
-    } else {
-        float sum = first ? 0.0f : ksum[cell];
-        float c = first ? 0.0f : kc[cell];
-        for (int k = 0; k < a.nsec; ++k) {
-            const SecDev &s = a.s[k];
+        if (lane < nq) {
+            const uint32_t *src = V + s.off + (int64_t)rbase * a.pitch + qlo + lane;
+            for (int rr = wv; rr < nr; rr += 4) tile[rr * BP_LP + lane] = src[(int64_t)rr * a.pitch];
+        }
+        __syncthreads();
+        const float scf = (float)s.scale;
+#pragma unroll
+        for (int c = 0; c < BP_CELLS; ++c) {
+            const int i = i0 + wv + 4 * c;
+            if (i >= a.H || j >= a.W) continue;
             int p, q;
             to_frame(s.kase, a.W, i, j, p, q);
-            int d;
-            double r;
-            col_offset(s.T, q, d, r);
-            const uint32_t *col = V + s.off + q;
-            const int ri = p - d - s.t0;
-            const float A = (float)ring_sum(col[(int64_t)ri * a.pitch], s.clip);
-            float vx = A;
-            if (r != 0.0) {
-                const float B = (float)ring_sum(col[(int64_t)(ri - 1) * a.pitch], s.clip);
-                const float rf = (float)r;
-                vx = __fadd_rn(__fmul_rn(1.0f - rf, A), __fmul_rn(rf, B));
+            const int cq = q - qlo;
+            const int d = col_d[cq];
+            const double r = col_r[cq];
+            const int row = p - d - s.t0 - rbase;
+            const double A = ring_sum(tile[row * BP_LP + cq], s.clip);
+            if (KAHAN) {
+                float vx = (float)A;
+                if (r != 0.0) {
+                    const float B = (float)ring_sum(tile[(row - 1) * BP_LP + cq], s.clip);
+                    const float rf = (float)r;
+                    vx = __fadd_rn(__fmul_rn(1.0f - rf, vx), __fmul_rn(rf, B));
+                }
+                const float term = __fmul_rn(scf, vx);
+                const float y = __fsub_rn(term, fc[c]);
+                const float t = __fadd_rn(fs[c], y);
+                fc[c] = __fsub_rn(__fsub_rn(t, fs[c]), y);
+                fs[c] = t;
+            } else {
+                double vx = A;
+                if (r != 0.0) {
+                    const double B = ring_sum(tile[(row - 1) * BP_LP + cq], s.clip);
+                    vx = (1.0 - r) * A + r * B;
+                }
+                acc[c] += s.scale * vx;
             }
-            const float term = __fmul_rn((float)s.scale, vx);
-            const float y = __fsub_rn(term, c);
-            const float t = __fadd_rn(sum, y);
-            c = __fsub_rn(__fsub_rn(t, sum), y);
-            sum = t;
         }
-        if (last) out[cell] = (double)sum - (double)c;
-        else { ksum[cell] = sum; kc[cell] = c; }
+    }
+#pragma unroll
+    for (int c = 0; c < BP_CELLS; ++c) {
+        const int i = i0 + wv + 4 * c;
+        if (i >= a.H || j >= a.W) continue;
+        const int64_t cell = (int64_t)i * a.W + j;
+        if (KAHAN) {
+            if (last) out[cell] = (double)fs[c] - (double)fc[c];
+            else { ksum[cell] = fs[c]; kc[cell] = fc[c]; }
+        } else {
+            out[cell] = acc[c];
+        }
     }
 }
 
@@ -580,16 +669,17 @@ static hipError_t set_lds(F f, size_t bytes) {
 }
 
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
-                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, hipStream_t st) {
+                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, hipStream_t st) {
     dim3 grid(maxRows, a.nsec);
     const size_t lds = sweep_lds_bytes(maxWx, f64);
     hipError_t e;
     if (f64) {
-        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES> : k_sweep<double, SWEEP_WAVES>;
+        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES> : k_sweep<double, SWEEP_WAVES, false>;
         if ((e = set_lds(f, lds)) != hipSuccess) return e;
         f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const double *)skw, V, tab64);
     } else {
-        auto f = scan ? k_sweep_scan<float, SWEEP_WAVES> : k_sweep<float, SWEEP_WAVES>;
+        auto f = scan ? k_sweep_scan<float, SWEEP_WAVES>
+                      : (rcp ? k_sweep<float, SWEEP_WAVES, true> : k_sweep<float, SWEEP_WAVES, false>);
         if ((e = set_lds(f, lds)) != hipSuccess) return e;
         f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const float *)skw, V, tab32);
     }
@@ -598,8 +688,9 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
 
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum, float *kahan_c,
                            int first, int last, hipStream_t st) {
-    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4);
-    k_backproj<<<grid, 256, 0, st>>>(a, V, out, kahan_sum, kahan_c, first, last);
+    dim3 grid((a.W + BP_T - 1) / BP_T, (a.H + BP_T - 1) / BP_T);
+    if (kahan_sum) k_backproj<true><<<grid, 256, 0, st>>>(a, V, out, kahan_sum, kahan_c, first, last);
+    else k_backproj<false><<<grid, 256, 0, st>>>(a, V, out, kahan_sum, kahan_c, first, last);
     return hipGetLastError();
 }
 

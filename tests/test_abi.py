@@ -55,6 +55,18 @@ def test_rejects_bad_scalars(tvs, kw, status):
     assert ei.value.status == status
 
 
+def test_rejects_bad_flag_combinations(tvs):
+    import torch  # noqa: F401  (device tensors are not needed: validation happens first)
+    L = tvs.lib()
+    d = np.zeros(4, np.float32)
+    out = np.zeros(4, np.float64)
+    vp = C.c_void_p
+    for flags in (0x10, tvs.FLAG_SLOPE_RCP | tvs.FLAG_SLOPE_F64, tvs.FLAG_SLOPE_RCP | tvs.FLAG_SWEEP_SCAN):
+        rc = L.tvs_total_viewshed_ex(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp),
+                                     flags, None, None)
+        assert rc == -1, flags
+
+
 def test_rejects_bad_grid(tvs):
     L = tvs.lib()
     out = np.zeros(4, np.float64)
@@ -66,6 +78,13 @@ def test_rejects_bad_grid(tvs):
     assert L.tvs_total_viewshed(d.ctypes.data_as(vp), 40000, 2, 10.0, 1.5, 4, math.inf,
                                 out.ctypes.data_as(vp)) == -4
     assert L.tvs_total_viewshed_async(None, 2, 2, 10.0, 1.5, 4, math.inf, None, None) == -1
+    tiny = np.zeros((3, 3), np.float32)
+    tiny[1, 1] = np.float32(1e-30)
+    with pytest.raises(tvs.TvsError) as ei:
+        tvs.total_viewshed(tiny, 10.0, 1.5, 4)
+    assert ei.value.status == -1
+    with pytest.raises(tvs.TvsError):
+        tvs.total_viewshed(np.zeros((3, 3), np.float32), 10.0, 1e-25, 4)
     bad = np.zeros((3, 3), np.float32)
     bad[2, 1] = np.inf
     with pytest.raises(tvs.TvsError) as ei:

@@ -91,6 +91,24 @@ def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
         assert bad.size == 0, f"k={k}: {len(bad)} samples differ, first {bad[:3].tolist()}"
 
 
+@pytest.mark.parametrize("h0", [0.0, -0.0, 1.5, -2.0])
+def test_sector_rays_signed_zeros_and_ties(tvs, orc, h0):
+    """Grids of +0/-0 and small integers with h0 = 0 give many exactly equal slopes (hidden under
+    the strict comparison) and zero slopes of both signs: the sweep's sign-bit tests must agree
+    with the oracle's comparisons bit for bit."""
+    rng = np.random.default_rng(99)
+    H, W = 41, 150
+    dem = np.round(rng.uniform(-2, 3, (H, W))).astype(np.float32)
+    dem[rng.uniform(size=(H, W)) < 0.5] = 0.0
+    dem = np.where(rng.uniform(size=(H, W)) < 0.5, np.float32(-0.0) * np.abs(dem), dem).astype(np.float32)
+    for n, R in ((8, INF), (12, 400.0)):
+        for k in range(n):
+            note(f"signed zeros h0={h0} n={n} R={R} k={k}")
+            g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k)
+            o = orc.sector_V(dem, 10.0, h0, n, R, k, prec=32)
+            assert np.array_equal(g, packed(o)), f"n={n} k={k}"
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
 def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind, seed=5)
@@ -98,6 +116,18 @@ def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
         note(f"sector_rays double H={H} W={W} n={n} R={R} k={k} kind={kind}")
         g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_F64)
         o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=64)
+        assert np.array_equal(g, packed(o)), f"k={k}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
+def test_sector_rays_bitexact_reciprocal_variant(tvs, orc, H, W, n, R, kind):
+    """TVS_FLAG_SLOPE_RCP (slope = float difference times float reciprocal of m) against the
+    oracle's float mode doing the same product."""
+    dem = _dem(H, W, kind, seed=6)
+    for k in _sectors(n):
+        note(f"sector_rays rcp H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_RCP)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=33)
         assert np.array_equal(g, packed(o)), f"k={k}"
 
 
@@ -123,6 +153,10 @@ def test_total_small(tvs, orc, H, W, n, R, kind):
     g64 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_F64)
     o64 = orc.total(dem, 10.0, 1.5, n, R, prec=64)
     np.testing.assert_allclose(g64, o64, rtol=1e-12, atol=0)
+    note(f"total rcp H={H} W={W} n={n} R={R} kind={kind}")
+    g33 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_RCP)
+    o33 = orc.total(dem, 10.0, 1.5, n, R, prec=33)
+    np.testing.assert_allclose(g33, o33, rtol=1e-12, atol=0)
 
 
 def test_flat_full_disc_on_gpu(tvs):
