@@ -35,6 +35,33 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_digest():
+    import hashlib
+
+    path = os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "tvs_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+
+
+def read_traffic(path, workload, flags):
+    """HBM bytes per sweep launch from a committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    scaled by a copy kernel of known size). None unless it was taken on this kernel source,
+    workload and flags."""
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    try:
+        if (fields.get("kernel_source_sha256") != kernel_source_digest() or fields.get("workload") != workload
+                or int(fields.get("flags", "-1")) != flags):
+            return None
+        return int(fields["hbm_read_bytes_per_launch"]) + int(fields["hbm_write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,7 +71,10 @@ def main():
     ap.add_argument("--flags", type=int, default=0, help="TVS_FLAG_* bits (0 = default float path)")
     ap.add_argument("--cpu-window", type=int, default=128, help="side of the centre window the oracle times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.json"))
+    ap.add_argument("--traffic-summary", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.md"))
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="before timing, copy this many MiB device-to-device (a plain copy kernel of known size "
+                         "that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -68,6 +98,16 @@ def main():
     d = torch.from_numpy(dem).cuda()
     torch.cuda.synchronize()
     log(f"workload {args.workload}: {H}x{W}, {w['n_sectors']} sectors, {evals:.3e} LoS evals/step")
+
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib << 18  # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.copy_calibration_mib} MiB done")
+        del src, dst
 
     for i in range(args.warmup):
         out = tvs.total_viewshed(d, *call, flags=args.flags)
@@ -101,14 +141,7 @@ def main():
     avg_sweep_s = sweep_ms / 1e3 / max(sweep_n, 1)
     ops_per_launch = OPS_PER_EVAL * evals * args.steps / max(sweep_n, 1)
     achieved = ops_per_launch / avg_sweep_s if sweep_n else None
-    traffic = None
-    if os.path.exists(args.traffic_json):
-        try:
-            tj = json.load(open(args.traffic_json))
-            if tj.get("flags", 0) == args.flags and tj.get("workload") == args.workload:
-                traffic = tj.get("bytes_per_launch")
-        except (OSError, ValueError):
-            traffic = None
+    traffic = read_traffic(args.traffic_summary, args.workload, args.flags)
     roofline = {
         "bound": "alu",
         "achieved": achieved / 1e12 if achieved else None,
@@ -164,6 +197,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64" if args.flags & tvs.FLAG_SLOPE_F64 else "f32",
+        "slope": ("double quotient" if args.flags & tvs.FLAG_SLOPE_F64 else
+                  "correctly rounded float quotient" if args.flags & tvs.FLAG_SLOPE_EXACT else
+                  "float difference x float reciprocal"),
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {H}x{W} diamond-square DEM (seed {w['seed']}, roughness {w['roughness']}, "

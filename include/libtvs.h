@@ -55,14 +55,15 @@ enum tvs_status {
     TVS_ERANGE = -4   /* grid side above 32767 */
 };
 
-/* Variant flags (the default, 0, is: float slopes with exactly rounded division, one
- * lane per POV in the sweep, double per-cell accumulation). */
+/* Variant flags. The default, 0, decides visibility in float (the paper's kernels declare the
+ * slope float, Alg. 7/8) with the slope formed as the float elevation difference times the float
+ * reciprocal of the index distance, steps one lane per POV in the sweep, and accumulates each
+ * cell in double. */
 #define TVS_FLAG_SLOPE_F64 0x1u   /* visibility decided in double from double elevations */
 #define TVS_FLAG_SWEEP_SCAN 0x2u  /* sweep with one lane per target and wavefront prefix-max */
 #define TVS_FLAG_ACC_KAHAN32 0x4u /* float Kahan-compensated per-cell accumulation */
-#define TVS_FLAG_SLOPE_RCP 0x8u   /* float slope as the difference times the float reciprocal of
-                                     the distance (one product instead of an exactly rounded
-                                     quotient; float sweep only) */
+#define TVS_FLAG_SLOPE_EXACT 0x8u /* float slope as the correctly rounded quotient of difference
+                                     and distance (an IEEE float division) */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for
@@ -121,7 +122,7 @@ int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double
                           double obs_height, int32_t n_sectors, double max_dist, double *d_out,
                           uint32_t flags, tvs_stats *stats, void *hip_stream);
 
-/* tvs_singular_viewshed_async with variant flags (TVS_FLAG_SLOPE_F64 only) and, when
+/* tvs_singular_viewshed_async with variant flags (TVS_FLAG_SLOPE_F64, TVS_FLAG_SLOPE_EXACT) and, when
  * d_ray_V is non-NULL, the per-line-of-sight ring sums: d_ray_V[2k] forward and [2k+1]
  * backward of sector k, packed as U | (e << 30) (U whole rings in index^2 units including
  * the POV ring, e in {0,1} clipped last ring of area rho^2 - K^2, K = ceil(rho) - 1). */

@@ -15,7 +15,7 @@ import numpy as np
 
 __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
-    "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_RCP", "Stats",
+    "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "Stats",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -24,7 +24,7 @@ SO_PATH = os.path.join(_HERE, "libtvs.so")
 FLAG_SLOPE_F64 = 0x1
 FLAG_SWEEP_SCAN = 0x2
 FLAG_ACC_KAHAN32 = 0x4
-FLAG_SLOPE_RCP = 0x8
+FLAG_SLOPE_EXACT = 0x8
 
 _STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
 

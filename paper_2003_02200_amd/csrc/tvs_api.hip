@@ -117,11 +117,9 @@ int check_host_dem(const float *dem, int rows, int cols) {
 }
 
 int check_flags(uint32_t flags, bool accumulation) {
-    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_RCP |
+    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT |
                            (accumulation ? TVS_FLAG_ACC_KAHAN32 : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
-    if ((flags & TVS_FLAG_SLOPE_RCP) && (flags & (TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN)))
-        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_RCP applies to the float lane-per-POV sweep only");
     return TVS_OK;
 }
 
@@ -265,7 +263,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
-    const bool rcp = (flags & TVS_FLAG_SLOPE_RCP) != 0;
+    const bool rcp = (flags & TVS_FLAG_SLOPE_EXACT) == 0;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     pool_keep_memory(dev);
@@ -360,6 +358,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
 int run_singular(const float *d_dem, int H, int W, double dx, double h0, int n, double R, int pi, int pj,
                  uint32_t flags, double *d_area, uint32_t *d_rayV, hipStream_t st) {
     const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
+    const bool rcp = (flags & TVS_FLAG_SLOPE_EXACT) == 0;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     pool_keep_memory(dev);
@@ -382,7 +381,7 @@ int run_singular(const float *d_dem, int H, int W, double dx, double h0, int n, 
         ChunkArgs a = chunk_args(S, c, H, W, pitch, h0);
         a.pov_i = pi;
         a.pov_j = pj;
-        HIPCHK(launch_singular(a, d_dem, rayV, f64, st));
+        HIPCHK(launch_singular(a, d_dem, rayV, f64, rcp, st));
         HIPCHK(launch_singular_sum(a, rayV, d_area, k0 == 0, st));
     }
     return TVS_OK;
@@ -455,7 +454,8 @@ int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, dou
     if (rc) return rc;
     if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
         return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, rows, cols);
-    if (flags & ~TVS_FLAG_SLOPE_F64) return fail(TVS_EINVAL, "unsupported flags 0x%x for the singular viewshed", flags);
+    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT))
+        return fail(TVS_EINVAL, "unsupported flags 0x%x for the singular viewshed", flags);
     return run_singular(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, flags,
                         d_area, d_ray_V, (hipStream_t)hip_stream);
 }

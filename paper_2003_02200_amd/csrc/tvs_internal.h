@@ -47,7 +47,8 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
                         const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, hipStream_t st);
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum,
                            float *kahan_c, int first, int last, hipStream_t st);
-hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, hipStream_t st);
+hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, bool rcp,
+                           hipStream_t st);
 hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first,
                                hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);

@@ -20,11 +20,12 @@
 // and the singular viewshed (Alg. 1-3) as a ray scan: one wavefront per line of sight, lanes =
 // 64 consecutive targets, the horizon carried by a wavefront prefix-max.
 //
-// Floating point: the float path rounds the interpolated elevation to float, forms h = z + h0,
-// d = z - h and the slope as the correctly rounded quotient d / m (reciprocal table, one
-// product and one FMA correction; exact for every integer m in range), and compares in float.
-// The double path does the same steps in double. Explicit _rn intrinsics keep the compiler
-// from contracting any step into an FMA.
+// Floating point: the float path rounds the interpolated elevation to float, forms h = z + h0
+// and d = z - h, and the slope as d times the float reciprocal of m (default) or as the
+// correctly rounded quotient d / m (exact mode: reciprocal, one product and one FMA
+// correction, exact for every integer m in range); visibility is compared in float. The
+// double path forms the correctly rounded double quotient. Explicit _rn intrinsics keep the
+// compiler from contracting any step into an FMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -46,8 +47,8 @@ __device__ __forceinline__ double slope_div(double d, double2 t) {
     double r = __fma_rn(-q, t.x, d);
     return __fma_rn(r, t.y, q);
 }
-// Variant slope: the float difference times the float reciprocal of m (one product; differs
-// from the correctly rounded quotient by at most one ulp).
+// Default float slope: the float difference times the float reciprocal of m (one product;
+// within one ulp of the correctly rounded quotient).
 __device__ __forceinline__ float slope_rcp(float d, float2 t) { return __fmul_rn(d, t.y); }
 template <bool RCP> __device__ __forceinline__ float slope(float d, float2 t) {
     return RCP ? slope_rcp(d, t) : slope_div(d, t);
@@ -376,7 +377,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
 
 // Comparison variant: one wavefront per POV and direction, lanes = 64 consecutive targets,
 // the running horizon is the exclusive wavefront prefix-max carried across 64-target chunks.
-template <typename Tz, int NW>
+template <typename Tz, int NW, bool RCP>
 __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const Tz *__restrict__ skw,
                                                         uint32_t *__restrict__ V,
                                                         const typename Tab<Tz>::type *__restrict__ tab) {
@@ -403,7 +404,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
             for (int m0 = 0; m0 < M; m0 += 64) {
                 const int m = m0 + lane + 1;
                 const bool ok = m <= M;
-                const Tz th = ok ? slope_div(sub_rn(zp[dir * m], h), tab[m - 1]) : neg_inf<Tz>();
+                const Tz th = ok ? slope<RCP>(sub_rn(zp[dir * m], h), tab[m - 1]) : neg_inf<Tz>();
                 const Tz incl = wave_prefix_max(th);
                 const Tz excl = vmax(carry, wave_shift_up(neg_inf<Tz>(), incl));
                 if (ok && th > excl) {
@@ -551,7 +552,7 @@ __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint3
 // (renormalised into [0,1) and snapped like Alg. 6's weights). A target is visible iff its
 // slope beats the maximum over all earlier targets: the exclusive wavefront prefix-max of the
 // chunk, combined with the maximum carried from earlier chunks.
-template <typename Tz>
+template <typename Tz, bool RCP>
 __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float *__restrict__ dem,
                                                   uint32_t *__restrict__ rayV) {
     const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float
                     interp(u, dr, Hx, [&](int v) { return dem[frame_index(s.kase, a.W, v, j)]; });
                 const Tz z = (Tz)z64;
                 const Tz dz = sub_rn(z, h);
-                if constexpr (sizeof(Tz) == 4) th = __fdiv_rn(dz, (float)m);
+                if constexpr (sizeof(Tz) == 4) th = RCP ? __fmul_rn(dz, __fdiv_rn(1.0f, (float)m)) : __fdiv_rn(dz, (float)m);
                 else th = __ddiv_rn(dz, (double)m);
             }
         }
@@ -674,11 +675,11 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
     const size_t lds = sweep_lds_bytes(maxWx, f64);
     hipError_t e;
     if (f64) {
-        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES> : k_sweep<double, SWEEP_WAVES, false>;
+        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES, false> : k_sweep<double, SWEEP_WAVES, false>;
         if ((e = set_lds(f, lds)) != hipSuccess) return e;
         f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const double *)skw, V, tab64);
     } else {
-        auto f = scan ? k_sweep_scan<float, SWEEP_WAVES>
+        auto f = scan ? (rcp ? k_sweep_scan<float, SWEEP_WAVES, true> : k_sweep_scan<float, SWEEP_WAVES, false>)
                       : (rcp ? k_sweep<float, SWEEP_WAVES, true> : k_sweep<float, SWEEP_WAVES, false>);
         if ((e = set_lds(f, lds)) != hipSuccess) return e;
         f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const float *)skw, V, tab32);
@@ -694,10 +695,12 @@ hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, f
     return hipGetLastError();
 }
 
-hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, hipStream_t st) {
+hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, bool rcp,
+                           hipStream_t st) {
     const int blocks = (2 * a.nsec + 3) / 4;
-    if (f64) k_singular<double><<<blocks, 256, 0, st>>>(a, dem, rayV);
-    else k_singular<float><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    if (f64) k_singular<double, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    else if (rcp) k_singular<float, true><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    else k_singular<float, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
     return hipGetLastError();
 }
 

@@ -3,7 +3,9 @@
 Bar (from the method's arithmetic):
 * per-sector skewed viewshed (integer ring sums U and clipped-ring counts e): bit-exact against
   the oracle taking the same decisions in the same precision -- float for the default path
-  (the paper's single-precision kernels), double for TVS_FLAG_SLOPE_F64;
+  (the paper's single-precision kernels; slope = difference times float reciprocal, oracle
+  prec=33) and for TVS_FLAG_SLOPE_EXACT (correctly rounded float quotient, prec=32), double for
+  TVS_FLAG_SLOPE_F64 (prec=64);
 * total viewshed map: equal to that oracle up to double summation order (rtol 1e-12);
 * against the all-double oracle: per-cell relative error <= 1e-4 on cells without a horizon
   flip, horizon flips (POV-sector pairs whose U or e differ) <= 1e-5 of all pairs.
@@ -18,6 +20,7 @@ from synth import cone, flat, fractal_dem, plane, workload_dem, WORKLOADS
 
 pytestmark = pytest.mark.gpu
 INF = math.inf
+P_DEFAULT, P_EXACT, P_DOUBLE = 33, 32, 64
 
 
 def note(msg):
@@ -85,10 +88,22 @@ def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
     for k in _sectors(n):
         note(f"sector_rays float H={H} W={W} n={n} R={R} k={k} kind={kind}")
         g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=32)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_DEFAULT)
         assert g.shape == o["U"].shape
         bad = np.argwhere(g != packed(o))
         assert bad.size == 0, f"k={k}: {len(bad)} samples differ, first {bad[:3].tolist()}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
+def test_sector_rays_bitexact_exact_division(tvs, orc, H, W, n, R, kind):
+    """TVS_FLAG_SLOPE_EXACT (correctly rounded float quotient) against the oracle's float
+    division mode."""
+    dem = _dem(H, W, kind, seed=6)
+    for k in _sectors(n):
+        note(f"sector_rays exact H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_EXACT)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_EXACT)
+        assert np.array_equal(g, packed(o)), f"k={k}"
 
 
 @pytest.mark.parametrize("h0", [0.0, -0.0, 1.5, -2.0])
@@ -104,9 +119,10 @@ def test_sector_rays_signed_zeros_and_ties(tvs, orc, h0):
     for n, R in ((8, INF), (12, 400.0)):
         for k in range(n):
             note(f"signed zeros h0={h0} n={n} R={R} k={k}")
-            g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k)
-            o = orc.sector_V(dem, 10.0, h0, n, R, k, prec=32)
-            assert np.array_equal(g, packed(o)), f"n={n} k={k}"
+            for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT)):
+                g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags)
+                o = orc.sector_V(dem, 10.0, h0, n, R, k, prec=prec)
+                assert np.array_equal(g, packed(o)), f"n={n} k={k} flags={flags}"
 
 
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
@@ -119,18 +135,6 @@ def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
         assert np.array_equal(g, packed(o)), f"k={k}"
 
 
-@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
-def test_sector_rays_bitexact_reciprocal_variant(tvs, orc, H, W, n, R, kind):
-    """TVS_FLAG_SLOPE_RCP (slope = float difference times float reciprocal of m) against the
-    oracle's float mode doing the same product."""
-    dem = _dem(H, W, kind, seed=6)
-    for k in _sectors(n):
-        note(f"sector_rays rcp H={H} W={W} n={n} R={R} k={k} kind={kind}")
-        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_RCP)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=33)
-        assert np.array_equal(g, packed(o)), f"k={k}"
-
-
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[1::3])
 def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
     """The lane-per-target sweep (wavefront prefix-max horizon) gives the same integers."""
@@ -138,8 +142,11 @@ def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
     for k in _sectors(n)[:6]:
         note(f"sector_rays scan H={H} W={W} n={n} R={R} k={k}")
         g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=32)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_DEFAULT)
         assert np.array_equal(g, packed(o)), f"k={k}"
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN | tvs.FLAG_SLOPE_EXACT)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_EXACT)
+        assert np.array_equal(g, packed(o)), f"k={k} exact"
 
 
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
@@ -147,16 +154,13 @@ def test_total_small(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind, seed=11)
     note(f"total H={H} W={W} n={n} R={R} kind={kind}")
     g = tvs.total_viewshed(dem, 10.0, 1.5, n, R)
-    o32 = orc.total(dem, 10.0, 1.5, n, R, prec=32)
-    np.testing.assert_allclose(g, o32, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, R, prec=P_DEFAULT), rtol=1e-12, atol=0)
+    note(f"total exact H={H} W={W} n={n} R={R} kind={kind}")
+    g32 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_EXACT)
+    np.testing.assert_allclose(g32, orc.total(dem, 10.0, 1.5, n, R, prec=P_EXACT), rtol=1e-12, atol=0)
     note(f"total f64 H={H} W={W} n={n} R={R} kind={kind}")
     g64 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_F64)
-    o64 = orc.total(dem, 10.0, 1.5, n, R, prec=64)
-    np.testing.assert_allclose(g64, o64, rtol=1e-12, atol=0)
-    note(f"total rcp H={H} W={W} n={n} R={R} kind={kind}")
-    g33 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_RCP)
-    o33 = orc.total(dem, 10.0, 1.5, n, R, prec=33)
-    np.testing.assert_allclose(g33, o33, rtol=1e-12, atol=0)
+    np.testing.assert_allclose(g64, orc.total(dem, 10.0, 1.5, n, R, prec=P_DOUBLE), rtol=1e-12, atol=0)
 
 
 def test_flat_full_disc_on_gpu(tvs):
@@ -174,7 +178,7 @@ def test_kahan_float_accumulation(tvs, orc):
     dem = fractal_dem(64, 21, 0.6, 900.0)
     note("kahan32 64x64 n=60")
     g = tvs.total_viewshed(dem, 10.0, 1.5, 60, 500.0, flags=tvs.FLAG_ACC_KAHAN32)
-    o = orc.total(dem, 10.0, 1.5, 60, 500.0, prec=32)
+    o = orc.total(dem, 10.0, 1.5, 60, 500.0, prec=P_DEFAULT)
     np.testing.assert_allclose(g, o, rtol=2e-6)
 
 
@@ -203,11 +207,12 @@ def test_singular(tvs, orc, H, W, n, R, pov):
     dem = fractal_dem(max(H, W), 17, 0.6, 600.0)[:H, :W].copy()
     i0, j0 = pov
     note(f"singular H={H} W={W} n={n} R={R} pov={pov}")
-    area, rays = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, rays=True)
-    o = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=32)
-    want = o["U"].astype(np.uint32) | (o["e"].astype(np.uint32) << np.uint32(30))
-    assert np.array_equal(rays, want)
-    assert area == pytest.approx(o["area"], rel=1e-12)
+    for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT)):
+        area, rays = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, flags=flags, rays=True)
+        o = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=prec)
+        want = o["U"].astype(np.uint32) | (o["e"].astype(np.uint32) << np.uint32(30))
+        assert np.array_equal(rays, want), flags
+        assert area == pytest.approx(o["area"], rel=1e-12)
     area64 = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, flags=tvs.FLAG_SLOPE_F64)
     o64 = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=64)
     assert area64 == pytest.approx(o64["area"], rel=1e-12)
@@ -241,8 +246,7 @@ def test_workload_128_full_map(tvs, orc):
     args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
     note("workload tvs128 total")
     g = tvs.total_viewshed(dem, *args)
-    o32 = orc.total(dem, *args, prec=32)
-    np.testing.assert_allclose(g, o32, rtol=1e-12)
+    np.testing.assert_allclose(g, orc.total(dem, *args, prec=P_DEFAULT), rtol=1e-12)
     o64 = orc.total(dem, *args, prec=64)
     note("workload tvs128 flips")
     flips, pairs = _flip_stats(tvs, orc, dem, *args, range(w["n_sectors"]))
@@ -276,7 +280,7 @@ def test_workload_2000_sampled(tvs, orc):
     worst32 = 0.0
     worst64 = 0.0
     for (i, j) in cells:
-        o32 = orc.total(dem, *args, prec=32, window=(i, j, 1, 1))[0, 0]
+        o32 = orc.total(dem, *args, prec=P_DEFAULT, window=(i, j, 1, 1))[0, 0]
         o64 = orc.total(dem, *args, prec=64, window=(i, j, 1, 1))[0, 0]
         worst32 = max(worst32, abs(g[i, j] - o32) / o32)
         worst64 = max(worst64, abs(g[i, j] - o64) / o64)

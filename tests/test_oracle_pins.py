@@ -40,17 +40,19 @@ def test_golden_row5(orc):
         R = INF if case["max_dist"] == "inf" else float(case["max_dist"])
         tv = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], R)
         np.testing.assert_allclose(tv[0] / (math.pi / 2), case["tvs_over_pi_half"], rtol=1e-13)
-        tv32 = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], R, prec=32)
-        np.testing.assert_allclose(tv32[0] / (math.pi / 2), case["tvs_over_pi_half"], rtol=1e-13)
+        for prec in (32, 33):
+            tvp = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], R, prec=prec)
+            np.testing.assert_allclose(tvp[0] / (math.pi / 2), case["tvs_over_pi_half"], rtol=1e-13)
 
 
 def test_golden_grid5(orc):
     """Hand-derived 5x5 example at 0/45/90/135 deg: pins axis orientation, case transforms and 1/cos^2."""
     g = json.load(open(os.path.join(GOLD, "grid5.json")))
     dem = np.array(g["dem"], np.float32)
-    tv = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], INF)
-    for i, j, v in g["cells_tvs_over_pi"]:
-        assert tv[i, j] / math.pi == pytest.approx(v, rel=1e-13)
+    for prec in (64, 32, 33):
+        tv = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], INF, prec=prec)
+        for i, j, v in g["cells_tvs_over_pi"]:
+            assert tv[i, j] / math.pi == pytest.approx(v, rel=1e-13)
 
 
 # ------------------------------------------------------------------ P1/P2: flat terrain
@@ -167,7 +169,7 @@ def test_clipped_ring_split(orc, R):
 
 # ------------------------------------------------------------------ P3: tilted plane
 
-@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("prec", [64, 32, 33])
 @pytest.mark.parametrize("n", [7, 12])
 def test_tilted_plane_interior_full_disc(orc, n, prec):
     """P3: interpolated samples of a plane lie on the plane, so all are visible. A wrong
@@ -217,7 +219,7 @@ def test_n1_n2_equal_row_and_column_walks(orc, R):
 
 # ------------------------------------------------------------------ P5: singular == total at n = 4
 
-@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("prec", [64, 32, 33])
 def test_n4_singular_equals_total(orc, prec):
     """P5: at 0/45/90/135 deg every skew weight is 0, so the two skewed POVs a cell blends
     collapse to the cell itself and the total viewshed equals the singular one exactly."""
@@ -243,7 +245,7 @@ def test_singular_close_to_total_on_smooth_terrain(orc):
 
 # ------------------------------------------------------------------ P6: brute force per pair
 
-@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("prec", [64, 32, 33])
 def test_running_max_equals_brute_force(orc, prec):
     """P6: 'visible iff the slope beats the running maximum' equals the O(M^2) definition
     'visible iff every earlier slope is strictly smaller', and the ring sum follows from it."""
@@ -340,8 +342,9 @@ def test_skewed_samples_lie_on_straight_lines(orc, n):
 
 # ------------------------------------------------------------------ P8/P9: symmetries
 
+@pytest.mark.parametrize("prec", [32, 33])
 @pytest.mark.parametrize("n", [4, 7, 10])
-def test_mirror_pairs_agree_exactly(orc, n):
+def test_mirror_pairs_agree_exactly(orc, n, prec):
     """P8: mirroring the grid left-right maps axis k to axis (n - k) mod n. For 0 < k, k != n/2
     the two base frames are the same array, so per-sector results agree bit for bit. The
     self-paired axes 0 and 90 deg (no skew) see a mirrored base frame: at 0 deg every row is
@@ -350,8 +353,8 @@ def test_mirror_pairs_agree_exactly(orc, n):
     dem = fractal_dem(19, 13, 0.6, 700.0)[:, :15].copy()
     mir = np.ascontiguousarray(np.fliplr(dem))
     for k in range(n):
-        a = orc.sector_V(dem, 10.0, 1.5, n, 90.0, k, prec=32)
-        b = orc.sector_V(mir, 10.0, 1.5, n, 90.0, (n - k) % n, prec=32)
+        a = orc.sector_V(dem, 10.0, 1.5, n, 90.0, k, prec=prec)
+        b = orc.sector_V(mir, 10.0, 1.5, n, 90.0, (n - k) % n, prec=prec)
         for key in ("U", "e", "valid"):
             if k == 0:
                 assert np.array_equal(a[key], b[key][:, ::-1])
@@ -490,16 +493,30 @@ def test_rejects_bad_input(orc):
         orc.total(bad, 10.0, 1.5, 4, INF)
 
 
-def test_fp32_decisions_rarely_differ_from_fp64(orc):
+@pytest.mark.parametrize("prec", [32, 33])
+def test_fp32_decisions_rarely_differ_from_fp64(orc, prec):
     """The single-precision visibility decision (the paper's float kernels) differs from the
     double one only at near-ties; on fractal terrain such horizon flips are rare."""
     dem = fractal_dem(64, 1, 0.6, 1500.0)
     flips = pairs = 0
     for k in (0, 17, 45, 62, 90, 133, 170):
         a = orc.sector_V(dem, 10.0, 1.5, 180, 640.0, k, prec=64)
-        b = orc.sector_V(dem, 10.0, 1.5, 180, 640.0, k, prec=32)
+        b = orc.sector_V(dem, 10.0, 1.5, 180, 640.0, k, prec=prec)
         v = a["valid"].astype(bool)
         pairs += int(v.sum())
         flips += int(np.sum((a["U"] != b["U"])[v] | (a["e"] != b["e"])[v]))
     assert pairs > 20000
     assert flips / pairs < 1e-3
+
+
+def test_reciprocal_slope_within_one_ulp_of_quotient(orc):
+    """prec 33 forms the float slope as the difference times the float reciprocal of m; on a
+    ray its slopes lie within one float ulp of prec 32's correctly rounded quotients."""
+    dem = fractal_dem(40, 8, 0.6, 900.0)
+    for k in (0, 3, 7):
+        a = orc.ray(dem, 10.0, 1.5, 12, INF, k, 0, 5, 2, 1, prec=32)
+        b = orc.ray(dem, 10.0, 1.5, 12, INF, k, 0, 5, 2, 1, prec=33)
+        ta = a["theta"].astype(np.float32)
+        tb = b["theta"].astype(np.float32)
+        assert a["M"] == b["M"] > 10
+        assert np.all(np.abs(ta.view(np.int32) - tb.view(np.int32)) <= 1)
