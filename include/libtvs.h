@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 1
+#define TVS_ABI_VERSION 2
 
 enum tvs_status {
     TVS_OK = 0,
@@ -57,13 +57,18 @@ enum tvs_status {
 
 /* Variant flags. The default, 0, decides visibility in float (the paper's kernels declare the
  * slope float, Alg. 7/8) with the slope formed as the float elevation difference times the float
- * reciprocal of the index distance, steps one lane per POV in the sweep, and accumulates each
- * cell in double. */
+ * reciprocal of the index distance, steps one lane per POV in the sweep, ends a group of 64 lines
+ * of sight early once no remaining target can rise above any of their horizons (results are
+ * those of the full walk: the bound uses only monotone roundings), and accumulates each cell in
+ * double. */
 #define TVS_FLAG_SLOPE_F64 0x1u   /* visibility decided in double from double elevations */
 #define TVS_FLAG_SWEEP_SCAN 0x2u  /* sweep with one lane per target and wavefront prefix-max */
 #define TVS_FLAG_ACC_KAHAN32 0x4u /* float Kahan-compensated per-cell accumulation */
 #define TVS_FLAG_SLOPE_EXACT 0x8u /* float slope as the correctly rounded quotient of difference
                                      and distance (an IEEE float division) */
+#define TVS_FLAG_NO_PRUNE 0x10u   /* walk every target in range, as Alg. 8 does (same results) */
+#define TVS_FLAG_COUNT_EVALS 0x20u /* total viewshed only, needs `stats`: count the line-of-sight
+                                      evaluations the sweep carries out into stats->sweep_evals_done */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for
@@ -81,6 +86,8 @@ typedef struct tvs_stats {
     int64_t reloc_bytes;    /* algorithmic bytes of the relocation: 4 read + element size written per sample */
     int64_t sweep_bytes;    /* algorithmic bytes of the sweep: element size read + 4 written per sample */
     int64_t scratch_bytes;  /* device scratch used */
+    int64_t sweep_evals_done; /* evaluations carried out by the sweep (TVS_FLAG_COUNT_EVALS), else 0;
+                                 equals los_evals with TVS_FLAG_NO_PRUNE */
 } tvs_stats;
 
 /* ABI version of the loaded library (TVS_ABI_VERSION of the build). */

@@ -15,7 +15,8 @@ import numpy as np
 
 __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
-    "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "Stats",
+    "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
+    "FLAG_COUNT_EVALS", "Stats",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -25,6 +26,8 @@ FLAG_SLOPE_F64 = 0x1
 FLAG_SWEEP_SCAN = 0x2
 FLAG_ACC_KAHAN32 = 0x4
 FLAG_SLOPE_EXACT = 0x8
+FLAG_NO_PRUNE = 0x10
+FLAG_COUNT_EVALS = 0x20
 
 _STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
 
@@ -41,6 +44,7 @@ class Stats(C.Structure):
         ("reloc_launches", C.c_int32), ("sweep_launches", C.c_int32), ("backproj_launches", C.c_int32),
         ("chunks", C.c_int32), ("los_evals", C.c_int64), ("pov_sector_pairs", C.c_int64),
         ("reloc_bytes", C.c_int64), ("sweep_bytes", C.c_int64), ("scratch_bytes", C.c_int64),
+        ("sweep_evals_done", C.c_int64),
     ]
 
     def as_dict(self):

@@ -117,8 +117,8 @@ int check_host_dem(const float *dem, int rows, int cols) {
 }
 
 int check_flags(uint32_t flags, bool accumulation) {
-    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT |
-                           (accumulation ? TVS_FLAG_ACC_KAHAN32 : 0u);
+    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_NO_PRUNE |
+                           (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
     return TVS_OK;
 }
@@ -264,12 +264,15 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
     const bool rcp = (flags & TVS_FLAG_SLOPE_EXACT) == 0;
+    const bool prune = (flags & TVS_FLAG_NO_PRUNE) == 0;
+    const bool count = (flags & TVS_FLAG_COUNT_EVALS) != 0;
+    if (count && !stats) return fail(TVS_EINVAL, "TVS_FLAG_COUNT_EVALS needs a stats argument");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     pool_keep_memory(dev);
     const int pitch = pitch_of(H, W);
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
-    if (sweep_lds_bytes(std::max(H, W), f64) > (size_t)lds_limit(dev))
+    if (sweep_lds_bytes(std::max(H, W), f64) + 64 > (size_t)lds_limit(dev))  // + the kernels' static LDS
         return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)",
                     std::max(H, W), f64 ? "double" : "float", lds_limit(dev));
 
@@ -283,7 +286,8 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const int tabN = std::max(H, W);  // entries for m = 1 .. max(H, W)
     const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
     const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
-    const size_t total = tabBytes + kahanBytes + 256 * 4 + maxChunk;
+    constexpr int kWorkSlots = 64;  // evaluation counters of the sweep (TVS_FLAG_COUNT_EVALS)
+    const size_t total = tabBytes + kahanBytes + 256 * 4 + kWorkSlots * 8 + maxChunk;
 
     Scratch scr;
     scr.st = st;
@@ -302,12 +306,14 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     double2 *tab64 = (double2 *)carve((size_t)tabN * sizeof(double2));
     float *ksum = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
     float *kc = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
+    unsigned long long *work = count ? (unsigned long long *)carve(kWorkSlots * 8) : nullptr;
     char *skwV = (char *)carve(maxChunk);
 
     Timer tm;
     tm.on = stats != nullptr;
     tm.st = st;
     HIPCHK(launch_divtab(tab32, tab64, tabN, st));
+    if (work) HIPCHK(launch_fill_u32((uint32_t *)work, 2 * kWorkSlots, 0u, st));
     int64_t evals = 0, pairs = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const Chunk &c = chunks[ci];
@@ -320,7 +326,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         HIPCHK(launch_relocate(a, c.maxWx, c.maxRows, d_dem, skw, f64, st));
         HIPCHK(tm.mark());
         HIPCHK(tm.begin(1));
-        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, rcp, st));
+        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st));
         HIPCHK(tm.mark());
         if (d_debugV) {
             const Sector &s = S[0];
@@ -351,6 +357,12 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         stats->reloc_bytes = pairs * (int64_t)(4 + elem);
         stats->sweep_bytes = pairs * (int64_t)(elem + 4);
         stats->scratch_bytes = (int64_t)total;
+        if (work) {
+            unsigned long long h[kWorkSlots];
+            HIPCHK(hipMemcpyAsync(h, work, sizeof(h), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            for (int x = 0; x < kWorkSlots; ++x) stats->sweep_evals_done += (int64_t)h[x];
+        }
     }
     return TVS_OK;
 }

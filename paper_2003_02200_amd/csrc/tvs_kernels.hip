@@ -217,17 +217,51 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
     case 2: xb = a.W - 1; xsu = -1; xsq = a.W; break;
     default: xb = a.W - 1; xsu = a.W; xsq = -1; break;
     }
+    // Staging: every thread issues all of its loads before its first LDS store, so a wavefront
+    // has up to 33 (48) reads in flight instead of one. Which rows and columns a wavefront
+    // stages depends only on wv, so the guards below are uniform branches.
+    const int lc = min(lane, ncol - 1);  // lanes past the tile's last column re-read it
     if (xsq == 1 || xsq == -1) {
         // base-frame rows are grid rows (reversed for case 3): coalesced along the row
-        if (lane < ncol) {
-            const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + lane) * xsq;
-            for (int rr = wv; rr < nr; rr += 4) tile[rr * RL_LP + lane] = src[(int64_t)rr * xsu];
+        constexpr int RPW = (RL_MAXR + 3) / 4;
+        const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + lc) * xsq;
+        float v[RPW];
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int rr = wv + 4 * i;
+            if (rr < nr) v[i] = src[(int64_t)rr * xsu];
+        }
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int rr = wv + 4 * i;
+            if (rr < nr && lane < ncol) tile[rr * RL_LP + lane] = v[i];
         }
     } else {
-        // base-frame columns are grid rows: read along them and transpose into LDS
-        for (int c = wv; c < ncol; c += 4) {
-            const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + c) * xsq;
-            for (int rr = lane; rr < nr; rr += 64) tile[rr * RL_LP + c] = src[rr * xsu];
+        // base-frame columns are grid rows: read along them (lanes = base-frame rows) and
+        // transpose into LDS; each wavefront takes 16 columns in two halves of 8
+        constexpr int RCH = (RL_MAXR + 63) / 64;
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+            float v[8][RCH];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = wv + 4 * (8 * half + i);
+                const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + min(c, ncol - 1)) * xsq;
+#pragma unroll
+                for (int k = 0; k < RCH; ++k) {
+                    const int rr = lane + 64 * k;
+                    if (64 * k < nr) v[i][k] = src[min(rr, nr - 1) * xsu];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int c = wv + 4 * (8 * half + i);
+#pragma unroll
+                for (int k = 0; k < RCH; ++k) {
+                    const int rr = lane + 64 * k;
+                    if (c < ncol && rr < nr) tile[rr * RL_LP + c] = v[i][k];
+                }
+            }
         }
     }
     __syncthreads();
@@ -244,6 +278,7 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
     const double w = __dsub_rn(1.0, r);
     Tz *out = skw + s.off + (int64_t)(r0 + rr) * a.pitch + q;
     const int64_t step = (int64_t)4 * a.pitch;
+#pragma unroll 4
     for (; rr <= tlast - tb; rr += 4, out += step) {
         const int u = tb + rr + d;
         const int uc = min(max(u, 0), Hx - 1);
@@ -283,32 +318,91 @@ struct RingAcc {
 // the LDS row; `mb` is the last step any lane of the wavefront needs (lanes whose row ends earlier
 // read -inf sentinels, which are never visible). Steps m < K add the whole ring 2m+1 to U; the
 // step m = K (the ring clipped at rho) is returned as 0/1. Steps run in blocks of 32 sharing one
-// scalar load of the {m, 1/m} table; each step is subtract, exactly rounded divide (3 VALU),
-// compare + add-with-carry into the bit mask, max.
-template <typename Tz, int DIR, bool RCP>
+// scalar load of the {m, 1/m} table; each step is subtract, slope, compare + add-with-carry into
+// the bit mask, max. Returns in `done` the number of steps taken.
+//
+// Early exit (PRUNE): before each block the wavefront stops when no target from step m on can
+// be visible on any live lane. `bnd` holds maxima of the row's elevations per 32-sample block,
+// accumulated away from the POVs (suffix maxima forward, prefix maxima backward), so
+// zs = bnd[(pbase + DIR m) / 32] bounds every elevation a lane still reads. Rounding is monotone:
+// for m' >= m, RN(z - h) <= RN(zs - h) and the slope of RN(zs - h) >= 0 does not grow with m', so
+// every remaining slope is at most max(slope(RN(zs - h), m), 0) (a negative difference gives a
+// negative slope). When that bound is <= the lane's horizon, no later target passes the strict
+// test, the clipped last ring included, and the ring sums are those of the full walk.
+template <typename Tz, int DIR, bool RCP, bool PRUNE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
-                                              const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U) {
-    Tz mx = neg_inf<Tz>();
+                                              const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
+                                              const Tz *bnd, int pbase, bool live, int &done) {
+    // a lane past the row end starts with a +inf horizon: it never sees a target and never
+    // holds back the early exit (its sums are discarded)
+    Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
     const int mfull = (mb == K) ? K - 1 : mb;
+    auto hidden_from = [&](int mm) -> bool {
+        const Tz zs = bnd[(pbase + DIR * mm) >> 5];
+        const Tz b = vmax(slope<RCP>(sub_rn(zs, h), tab[mm - 1]), (Tz)0);
+        // every lane of the (fully active) wavefront agrees; a wave-uniform answer keeps the
+        // step counter, and with it the table loads, scalar
+        return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
+    };
     RingAcc ra;
     int m = 1;
+    bool stop = false;
     for (; m + 31 <= mfull; m += 32) {
+        if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads on the scalar path
+        if (PRUNE && m > 1 && hidden_from(m)) {
+            stop = true;
+            break;
+        }
         const auto *t = static_cast<const typename Tab<Tz>::type *>(__builtin_assume_aligned(tab + (m - 1), 256));
         uint32_t bits = 0;
 #pragma unroll
         for (int s = 0; s < 32; ++s) vis_step(slope<RCP>(sub_rn(zp[DIR * (m + s)], h), t[s]), mx, bits);
         ra.add(bits, m);
     }
+    if (PRUNE && !stop && m > 1 && m <= mb) stop = hidden_from(m);
     uint32_t acc = ra.total();
-    for (; m <= mfull; ++m) {
-        const Tz th = slope<RCP>(sub_rn(zp[DIR * m], h), tab[m - 1]);
-        acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
-        mx = vmax(mx, th);
+    uint32_t e = 0;
+    if (!stop) {
+        for (; m <= mfull; ++m) {
+            const Tz th = slope<RCP>(sub_rn(zp[DIR * m], h), tab[m - 1]);
+            acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
+            mx = vmax(mx, th);
+        }
+        if (mb == K && K >= 1) e = slope<RCP>(sub_rn(zp[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
     }
     U += acc;
-    uint32_t e = 0;
-    if (mb == K && K >= 1) e = slope<RCP>(sub_rn(zp[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
+    done = stop ? m - 1 : mb;
     return e;
+}
+
+// Per-block elevation maxima of a row of nt samples (followed by -inf sentinels): pre[b] is the
+// maximum over blocks 0..b, suf[b] over blocks b..nb-1, each scanned by one wavefront with the
+// wavefront prefix-max.
+template <typename Tz>
+__device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre) {
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        Tz m = z[32 * b];
+#pragma unroll
+        for (int i = 1; i < 32; ++i) m = vmax(m, z[32 * b + i]);
+        suf[b] = m;
+        pre[b] = m;
+    }
+    __syncthreads();
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (wv < 2) {
+        Tz *arr = wv == 0 ? pre : suf;
+        Tz carry = neg_inf<Tz>();
+        for (int c = 0; c < nb; c += 64) {
+            const int i = c + lane;
+            const int b = wv == 0 ? i : nb - 1 - i;  // wavefront 1 scans from the right
+            Tz x = i < nb ? arr[b] : neg_inf<Tz>();
+            x = vmax(wave_prefix_max(x), carry);
+            if (i < nb) arr[b] = x;
+            carry = lane63(x);
+        }
+    }
+    __syncthreads();
 }
 
 template <typename Tz> __device__ __forceinline__ Tz h0_of(const ChunkArgs &a);
@@ -343,35 +437,56 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
     return nt;
 }
 
-template <typename Tz, int NW, bool RCP>
+template <typename Tz, int NW, bool RCP, bool PRUNE>
 __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
-                                                   const typename Tab<Tz>::type *__restrict__ tab) {
+                                                   const typename Tab<Tz>::type *__restrict__ tab,
+                                                   unsigned long long *__restrict__ work) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Tz *row = reinterpret_cast<Tz *>(lds_raw);
+    __shared__ unsigned long long wg_work;
     const SecDev &s = a.s[blockIdx.y];
     if ((int)blockIdx.x >= s.nrows) return;
     const int ri = row_of_block(blockIdx.x, s.nrows);
     int jlo;
     const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
     if (nt == 0) return;
+    const int nb = (nt + 31) >> 5;
+    Tz *suf = row + nt + 2 * TVS_SWEEP_PAD;
+    Tz *pre = suf + nb;
+    if (PRUNE) block_bounds(row + TVS_SWEEP_PAD, nb, suf, pre);
+    if (work && threadIdx.x == 0) wg_work = 0;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int K = s.K;
     const Tz h0 = h0_of<Tz>(a);
     const int nseg = (nt + 63) >> 6;
     uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
+    uint32_t evals = 0;  // line-of-sight evaluations this lane carried out (with work counting)
     for (int sg = wv; sg < nseg; sg += NW) {
-        const int q = (sg << 6) + lane;
+        const int q0 = sg << 6;
+        const int q = q0 + lane;
+        const bool live = q < nt;
         const Tz *zp = row + TVS_SWEEP_PAD + q;
         const Tz h = add_rn(zp[0], h0);
         uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
         uint32_t e = (K >= 1) ? 0u : 2u;
-        const int fwd = min(K, nt - 1 - (sg << 6));
-        const int bwd = min(K, min(nt - 1, (sg << 6) + 63));
-        e += sweep_dir<Tz, +1, RCP>(zp, h, fwd, K, tab, U);
-        e += sweep_dir<Tz, -1, RCP>(zp, h, bwd, K, tab, U);
-        if (q < nt) dst[q] = U | (e << 30);
+        const int top = min(nt - 1, q0 + 63);
+        const int fwd = min(K, nt - 1 - q0);
+        const int bwd = min(K, top);
+        int df, db;
+        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, q0, live, df);
+        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, top, live, db);
+        if (live) dst[q] = U | (e << 30);
+        if (work && live) evals += (uint32_t)(min(df, min(K, nt - 1 - q)) + min(db, min(K, q)));
+    }
+    if (work) {
+        // one atomic per workgroup, spread over 64 counters
+        const uint32_t wsum = wave_sum_u32(evals);
+        __syncthreads();
+        if (lane == 0) atomicAdd(&wg_work, (unsigned long long)wsum);
+        __syncthreads();
+        if (threadIdx.x == 0) atomicAdd(&work[(blockIdx.x + 7 * blockIdx.y) & 63], wg_work);
     }
 }
 
@@ -380,7 +495,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
 template <typename Tz, int NW, bool RCP>
 __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const Tz *__restrict__ skw,
                                                         uint32_t *__restrict__ V,
-                                                        const typename Tab<Tz>::type *__restrict__ tab) {
+                                                        const typename Tab<Tz>::type *__restrict__ tab,
+                                                        unsigned long long *__restrict__ work) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Tz *row = reinterpret_cast<Tz *>(lds_raw);
     const SecDev &s = a.s[blockIdx.y];
@@ -394,6 +510,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
     const int K = s.K;
     const Tz h0 = h0_of<Tz>(a);
     uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
+    unsigned long long evals = 0;
     for (int q = wv; q < nt; q += NW) {
         const Tz *zp = row + TVS_SWEEP_PAD + q;
         const Tz h = add_rn(zp[0], h0);
@@ -420,7 +537,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
             if (K >= 1) U += 2u; else e += 2u;
             dst[q] = U | (e << 30);
         }
+        evals += min(K, nt - 1 - q) + min(K, q);  // every target in range is evaluated
     }
+    if (work && lane == 0) atomicAdd(&work[(blockIdx.x + 7 * blockIdx.y) & 63], evals);
 }
 
 // ----------------------------------------------------------------------- back-projection
@@ -640,7 +759,8 @@ __global__ void k_singular_sum(const ChunkArgs a, const uint32_t *__restrict__ r
 constexpr int SWEEP_WAVES = 4;
 
 size_t sweep_lds_bytes(int maxWx, bool f64) {
-    return (size_t)(maxWx + 2 * TVS_SWEEP_PAD) * (f64 ? sizeof(double) : sizeof(float));
+    // row with sentinels, then the per-block suffix and prefix maxima of the early exit
+    return (size_t)(maxWx + 2 * TVS_SWEEP_PAD + 2 * ((maxWx + 31) / 32)) * (f64 ? sizeof(double) : sizeof(float));
 }
 
 hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st) {
@@ -669,22 +789,32 @@ static hipError_t set_lds(F f, size_t bytes) {
                                (int)bytes);
 }
 
-hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
-                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, hipStream_t st) {
-    dim3 grid(maxRows, a.nsec);
-    const size_t lds = sweep_lds_bytes(maxWx, f64);
-    hipError_t e;
-    if (f64) {
-        auto f = scan ? k_sweep_scan<double, SWEEP_WAVES, false> : k_sweep<double, SWEEP_WAVES, false>;
-        if ((e = set_lds(f, lds)) != hipSuccess) return e;
-        f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const double *)skw, V, tab64);
-    } else {
-        auto f = scan ? (rcp ? k_sweep_scan<float, SWEEP_WAVES, true> : k_sweep_scan<float, SWEEP_WAVES, false>)
-                      : (rcp ? k_sweep<float, SWEEP_WAVES, true> : k_sweep<float, SWEEP_WAVES, false>);
-        if ((e = set_lds(f, lds)) != hipSuccess) return e;
-        f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const float *)skw, V, tab32);
-    }
+template <typename Tz>
+static hipError_t sweep_go(void (*f)(ChunkArgs, const Tz *, uint32_t *, const typename Tab<Tz>::type *,
+                                     unsigned long long *),
+                           dim3 grid, size_t lds, hipStream_t st, const ChunkArgs &a, const void *skw, uint32_t *V,
+                           const typename Tab<Tz>::type *tab, unsigned long long *work) {
+    hipError_t e = set_lds(f, lds);
+    if (e != hipSuccess) return e;
+    f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const Tz *)skw, V, tab, work);
     return hipGetLastError();
+}
+
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
+                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
+                        unsigned long long *work, hipStream_t st) {
+    const dim3 grid(maxRows, a.nsec);
+    const size_t lds = sweep_lds_bytes(maxWx, f64);
+    constexpr int NW = SWEEP_WAVES;
+    if (f64) {
+        auto f = scan ? k_sweep_scan<double, NW, false>
+                      : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
+        return sweep_go<double>(f, grid, lds, st, a, skw, V, tab64, work);
+    }
+    auto f = scan ? (rcp ? k_sweep_scan<float, NW, true> : k_sweep_scan<float, NW, false>)
+                  : rcp ? (prune ? k_sweep<float, NW, true, true> : k_sweep<float, NW, true, false>)
+                        : (prune ? k_sweep<float, NW, false, true> : k_sweep<float, NW, false, false>);
+    return sweep_go<float>(f, grid, lds, st, a, skw, V, tab32, work);
 }
 
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum, float *kahan_c,

@@ -149,6 +149,72 @@ def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
         assert np.array_equal(g, packed(o)), f"k={k} exact"
 
 
+def _walled(H, W, seed):
+    """Low noisy ground with a few tall walls and towers: lines of sight that pass a wall see
+    nothing more, so the sweep's early exit fires in the middle of rows."""
+    rng = np.random.default_rng(seed)
+    dem = rng.uniform(0, 6, (H, W)).astype(np.float32)
+    for _ in range(4):
+        c = int(rng.integers(0, W))
+        dem[:, c:c + 2] += np.float32(rng.uniform(200, 900))
+    for _ in range(6):
+        i, j = int(rng.integers(0, H)), int(rng.integers(0, W))
+        dem[max(0, i - 3):i + 3, max(0, j - 3):j + 3] += np.float32(rng.uniform(300, 2000))
+    return dem
+
+
+EXIT_CASES = [
+    # (H, W, n, R, terrain): long rows so that exits land in blocks, before the tail and at K
+    (40, 400, 6, INF, "walled"),
+    (400, 40, 6, 1500.0, "walled"),
+    (90, 333, 10, 777.0, "fractal"),
+    (64, 700, 3, 3205.0, "walled"),
+    (257, 257, 24, 2570.0, "fractal"),
+]
+
+
+def _exit_dem(H, W, kind, seed):
+    if kind == "walled":
+        return _walled(H, W, seed)
+    return fractal_dem(max(H, W), seed, 0.7, 2500.0)[:H, :W].copy()
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES)
+def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
+    """The sweep's early exit changes no ring sum: pruned and full walks agree bit for bit with
+    each other and with the oracle, in all three slope precisions, for observers above and
+    below ground."""
+    dem = _exit_dem(H, W, kind, seed=H + W)
+    for h0 in (1.5, -3.0, 40.0):
+        for k in range(n):
+            note(f"early exit H={H} W={W} n={n} R={R} kind={kind} h0={h0} k={k}")
+            for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT), (tvs.FLAG_SLOPE_F64, P_DOUBLE)):
+                g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags)
+                full = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags | tvs.FLAG_NO_PRUNE)
+                assert np.array_equal(g, full), f"k={k} flags={flags}: pruned and full walks differ"
+                o = orc.sector_V(dem, 10.0, h0, n, R, k, prec=prec)
+                assert np.array_equal(g, packed(o)), f"k={k} flags={flags}"
+
+
+@pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES[:3])
+def test_evaluation_counts(tvs, H, W, n, R, kind):
+    """The sweep's own count of evaluations: the closed form without the early exit (and for the
+    lane-per-target variant), fewer with it; the maps are identical."""
+    dem = _exit_dem(H, W, kind, seed=7)
+    ev, _ = tvs.los_evals(H, W, 10.0, n, R)
+    note(f"evaluation counts H={H} W={W} n={n} R={R}")
+    full, st_full = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_NO_PRUNE | tvs.FLAG_COUNT_EVALS,
+                                       stats=True)
+    assert st_full.sweep_evals_done == ev == st_full.los_evals
+    _, st_scan = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SWEEP_SCAN | tvs.FLAG_COUNT_EVALS,
+                                    stats=True)
+    assert st_scan.sweep_evals_done == ev
+    pr, st = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_COUNT_EVALS, stats=True)
+    assert 0 < st.sweep_evals_done < ev
+    np.testing.assert_array_equal(pr, full)
+    print(f"{kind} {H}x{W}: evaluations carried out {st.sweep_evals_done / ev:.3f} of {ev}", flush=True)
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
 def test_total_small(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind, seed=11)
@@ -272,6 +338,11 @@ def test_workload_2000_sampled(tvs, orc):
     out = tvs.total_viewshed(d, *args)
     torch.cuda.synchronize()
     g = out.cpu().numpy()
+    note("workload tvs2000 total without the early exit")
+    full = tvs.total_viewshed(d, *args, flags=tvs.FLAG_NO_PRUNE)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(full.cpu().numpy(), g)
+    del full
     R = w["max_dist"]
     assert np.all(np.isfinite(g)) and np.all(g > 0) and np.all(g <= math.pi * R * R * (1 + 1e-12))
     rng = np.random.default_rng(2000)
