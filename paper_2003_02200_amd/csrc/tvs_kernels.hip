@@ -173,124 +173,144 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
 }
 
 // --------------------------------------------------------------------------- relocation
-// Output tile: 64 skewed rows x 64 columns of one sector per 256-thread workgroup. The base
-// frame rows it needs, [t + d_j, t + d_j + 1] over the tile, span at most 64 + 66 rows; they
-// are staged in LDS (row pitch 65 words so the transposed stores of cases 1/2 spread over
-// all banks), then every thread interpolates its column for 16 rows and stores them along
-// the skewed row (64 consecutive columns per wavefront).
-constexpr int RL_TW = 64;
-constexpr int RL_TH = 64;
+// A workgroup owns a strip of 64 base-frame columns of one sector and walks down RL_SEG of its
+// skewed rows in batches of 32. Skewed row t of column j blends base rows t + d_j and t + d_j + 1,
+// and over 64 columns d_j spans at most 64, so a batch needs at most 32 + 65 consecutive base
+// rows. They sit in an LDS ring of 128 rows (slot u mod 128, row pitch 65 words so that the
+// transposed stores of cases 1/2 spread over the banks); every base row is read from the DEM
+// once per workgroup, clamped to the frame. While a batch is interpolated, the 32 base rows the
+// next batch adds are already in flight into registers; they replace rows no later batch needs.
+// Each thread interpolates one column and stores along the skewed row (64 consecutive columns
+// per wavefront).
+constexpr int RL_TW = 64;     // columns per strip
+constexpr int RL_TB = 32;     // skewed rows per batch (= base rows added per batch)
+constexpr int RL_RING = 128;  // ring rows: >= RL_TB + 65 rows in use + RL_TB rows arriving
 constexpr int RL_LP = RL_TW + 1;
-constexpr int RL_MAXR = RL_TH + RL_TW + 3;
+constexpr int RL_SEG = 512;   // skewed rows per workgroup
+
+struct RelocFrame {
+    const float *dem;
+    int64_t xb;   // X[u][q] = dem[xb + u * xsu + q * xsq]
+    int xsu, xsq;
+    int Hx, j0, ncol;
+};
+
+// Base rows u0 .. u0 + 31 (clamped to the frame) of the strip: 8 values per thread.
+__device__ __forceinline__ void reloc_load(const RelocFrame &f, int u0, int wv, int lane, float (&v)[8]) {
+    if (f.xsq == 1 || f.xsq == -1) {
+        // base rows are grid rows: wavefront wv takes rows u0 + wv + 4i, lanes along the row
+        const int64_t col = (int64_t)(f.j0 + min(lane, f.ncol - 1)) * f.xsq;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int u = min(max(u0 + wv + 4 * i, 0), f.Hx - 1);
+            v[i] = f.dem[f.xb + (int64_t)u * f.xsu + col];
+        }
+    } else {
+        // base rows are grid columns: a half-wavefront reads 32 consecutive base rows of one base
+        // column (one grid row), base column c = (lane >> 5) + 2 (wv + 4i)
+        const int u = min(max(u0 + (lane & 31), 0), f.Hx - 1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int c = (lane >> 5) + 2 * (wv + 4 * i);
+            v[i] = f.dem[f.xb + (int64_t)u * f.xsu + (int64_t)(f.j0 + min(c, f.ncol - 1)) * f.xsq];
+        }
+    }
+}
+
+__device__ __forceinline__ void reloc_store(const RelocFrame &f, int u0, int wv, int lane, const float (&v)[8],
+                                            float *ring) {
+    if (f.xsq == 1 || f.xsq == -1) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+            if (lane < f.ncol) ring[((u0 + wv + 4 * i) & (RL_RING - 1)) * RL_LP + lane] = v[i];
+    } else {
+        const int slot = (u0 + (lane & 31)) & (RL_RING - 1);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int c = (lane >> 5) + 2 * (wv + 4 * i);
+            if (c < f.ncol) ring[slot * RL_LP + c] = v[i];
+        }
+    }
+}
 
 template <typename Tz>
 __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float *__restrict__ dem,
                                                   Tz *__restrict__ skw) {
-    __shared__ float tile[RL_MAXR * RL_LP];
+    __shared__ float ring[RL_RING * RL_LP];
     const SecDev &s = a.s[blockIdx.z];
-    int Hx, Wx;
-    frame_dims(s.kase, a.H, a.W, Hx, Wx);
-    const int j0 = blockIdx.x * RL_TW;
-    const int r0 = blockIdx.y * RL_TH;
-    if (j0 >= Wx || r0 >= s.nrows) return;
-    const int tb = s.t0 + r0;
-    const int te = min(tb + RL_TH - 1, Hx - 1);
-    const int jl = min(j0 + RL_TW - 1, Wx - 1);
+    RelocFrame f;
+    int Wx;
+    frame_dims(s.kase, a.H, a.W, f.Hx, Wx);
+    f.j0 = blockIdx.x * RL_TW;
+    if (f.j0 >= Wx) return;
+    const int jl = min(f.j0 + RL_TW - 1, Wx - 1);
+    f.ncol = jl - f.j0 + 1;
+    f.dem = dem;
+    switch (s.kase) {
+    case 0: f.xb = 0; f.xsu = a.W; f.xsq = 1; break;
+    case 1: f.xb = 0; f.xsu = 1; f.xsq = a.W; break;
+    case 2: f.xb = a.W - 1; f.xsu = -1; f.xsq = a.W; break;
+    default: f.xb = a.W - 1; f.xsu = a.W; f.xsq = -1; break;
+    }
     int dlo, dhi;
     double rlo, rhi;
-    col_offset(s.T, j0, dlo, rlo);
+    col_offset(s.T, f.j0, dlo, rlo);
     col_offset(s.T, jl, dhi, rhi);
-    // no sample of the tile exists: every column's rows lie below -1 or above Hx-1
-    if (te + dhi < -1 || tb + dlo > Hx - 1) return;
-    const int ua = min(max(tb + dlo, 0), Hx - 1);
-    const int ub = min(max(te + dhi + 1, 0), Hx - 1);
-    const int nr = ub - ua + 1;
+    // skewed rows with a sample in the strip: t + d_j in [-1, Hx - 1] for some column j
+    const int tS = max(s.t0 + (int)blockIdx.y * RL_SEG, max(s.t0, -1 - dhi));
+    const int tE = min(s.t0 + (int)blockIdx.y * RL_SEG + RL_SEG - 1, min(s.t0 + s.nrows - 1, f.Hx - 1 - dlo));
+    if (tS > tE) return;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int ncol = jl - j0 + 1;
-    // base-frame cell X[u][q] = dem[xb + u * xsu + q * xsq]
-    int64_t xb;
-    int xsu, xsq;
-    switch (s.kase) {
-    case 0: xb = 0; xsu = a.W; xsq = 1; break;
-    case 1: xb = 0; xsu = 1; xsq = a.W; break;
-    case 2: xb = a.W - 1; xsu = -1; xsq = a.W; break;
-    default: xb = a.W - 1; xsu = a.W; xsq = -1; break;
-    }
-    // Staging: every thread issues all of its loads before its first LDS store, so a wavefront
-    // has up to 33 (48) reads in flight instead of one. Which rows and columns a wavefront
-    // stages depends only on wv, so the guards below are uniform branches.
-    const int lc = min(lane, ncol - 1);  // lanes past the tile's last column re-read it
-    if (xsq == 1 || xsq == -1) {
-        // base-frame rows are grid rows (reversed for case 3): coalesced along the row
-        constexpr int RPW = (RL_MAXR + 3) / 4;
-        const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + lc) * xsq;
-        float v[RPW];
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int rr = wv + 4 * i;
-            if (rr < nr) v[i] = src[(int64_t)rr * xsu];
-        }
-#pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int rr = wv + 4 * i;
-            if (rr < nr && lane < ncol) tile[rr * RL_LP + lane] = v[i];
-        }
-    } else {
-        // base-frame columns are grid rows: read along them (lanes = base-frame rows) and
-        // transpose into LDS; each wavefront takes 16 columns in two halves of 8
-        constexpr int RCH = (RL_MAXR + 63) / 64;
-#pragma unroll
-        for (int half = 0; half < 2; ++half) {
-            float v[8][RCH];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int c = wv + 4 * (8 * half + i);
-                const float *src = dem + xb + (int64_t)ua * xsu + (int64_t)(j0 + min(c, ncol - 1)) * xsq;
-#pragma unroll
-                for (int k = 0; k < RCH; ++k) {
-                    const int rr = lane + 64 * k;
-                    if (64 * k < nr) v[i][k] = src[min(rr, nr - 1) * xsu];
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int c = wv + 4 * (8 * half + i);
-#pragma unroll
-                for (int k = 0; k < RCH; ++k) {
-                    const int rr = lane + 64 * k;
-                    if (c < ncol && rr < nr) tile[rr * RL_LP + c] = v[i][k];
-                }
-            }
-        }
+    const int uA = tS + dlo;  // first base row any batch reads
+    {
+        float v0[8], v1[8], v2[8], v3[8];
+        reloc_load(f, uA, wv, lane, v0);
+        reloc_load(f, uA + 32, wv, lane, v1);
+        reloc_load(f, uA + 64, wv, lane, v2);
+        reloc_load(f, uA + 96, wv, lane, v3);
+        reloc_store(f, uA, wv, lane, v0, ring);
+        reloc_store(f, uA + 32, wv, lane, v1, ring);
+        reloc_store(f, uA + 64, wv, lane, v2, ring);
+        reloc_store(f, uA + 96, wv, lane, v3, ring);
     }
     __syncthreads();
-    if (lane >= ncol) return;
-    const int q = j0 + lane;
+    const int q = f.j0 + min(lane, f.ncol - 1);
     int d;
     double r;
     col_offset(s.T, q, d, r);
     // existing rows of this column: u = t + d in [-1 (only if r > 0), Hx - 1]
-    const int tfirst = max(tb, (r != 0.0 ? -1 : 0) - d);
-    const int tlast = min(te, Hx - 1 - d);
-    int rr = wv + (((tfirst - tb - wv) + 3) >> 2 << 2);  // first rr >= tfirst - tb with rr = wv mod 4
-    if (rr < tfirst - tb) rr += 4;
+    const int tfirst = (r != 0.0 ? -1 : 0) - d;
+    const int tlast = f.Hx - 1 - d;
     const double w = __dsub_rn(1.0, r);
-    Tz *out = skw + s.off + (int64_t)(r0 + rr) * a.pitch + q;
-    const int64_t step = (int64_t)4 * a.pitch;
-#pragma unroll 4
-    for (; rr <= tlast - tb; rr += 4, out += step) {
-        const int u = tb + rr + d;
-        const int uc = min(max(u, 0), Hx - 1);
-        const float av = tile[(uc - ua) * RL_LP + lane];
-        double z = (double)av;
-        if (r != 0.0 && u >= 0 && u < Hx - 1) {
-            const float bv = tile[(u + 1 - ua) * RL_LP + lane];
-            z = __dadd_rn(__dmul_rn(w, (double)av), __dmul_rn(r, (double)bv));
+    const bool mine = lane < f.ncol;
+    const int nb = (tE - tS) / RL_TB + 1;
+    for (int b = 0; b < nb; ++b) {
+        const int tb = tS + b * RL_TB;
+        float v[8];
+        const bool more = b + 1 < nb;
+        if (more) reloc_load(f, uA + RL_RING + b * RL_TB, wv, lane, v);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int t = tb + wv + 4 * i;
+            if (mine && t <= tE && t >= tfirst && t <= tlast) {
+                const int u = t + d;
+                const float av = ring[(u & (RL_RING - 1)) * RL_LP + lane];
+                double z = (double)av;
+                if (r != 0.0 && u >= 0 && u < f.Hx - 1) {
+                    const float bv = ring[((u + 1) & (RL_RING - 1)) * RL_LP + lane];
+                    z = __dadd_rn(__dmul_rn(w, (double)av), __dmul_rn(r, (double)bv));
+                }
+                // + 0 turns a -0 elevation into +0 (no other value changes): the sweep's sign
+                // tests rely on slopes never being -0
+                skw[s.off + (int64_t)(t - s.t0) * a.pitch + q] = add_rn((Tz)z, (Tz)0);
+            }
         }
-        // + 0 turns a -0 elevation into +0 (no other value changes): the sweep's sign tests
-        // rely on slopes never being -0
-        *out = add_rn((Tz)z, (Tz)0);
+        if (more) {
+            __syncthreads();
+            reloc_store(f, uA + RL_RING + b * RL_TB, wv, lane, v, ring);
+            __syncthreads();
+        }
     }
 }
 
@@ -776,7 +796,7 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
 
 hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw, bool f64,
                            hipStream_t st) {
-    dim3 grid((maxWx + RL_TW - 1) / RL_TW, (maxRows + RL_TH - 1) / RL_TH, a.nsec);
+    dim3 grid((maxWx + RL_TW - 1) / RL_TW, (maxRows + RL_SEG - 1) / RL_SEG, a.nsec);
     if (f64) k_relocate<double><<<grid, 256, 0, st>>>(a, dem, (double *)skw);
     else k_relocate<float><<<grid, 256, 0, st>>>(a, dem, (float *)skw);
     return hipGetLastError();
