@@ -51,7 +51,9 @@
  * float division, compared in float. Ring sums and areas stay in double. prec = 33 is the
  * same float decision with the slope formed as the float difference times the float
  * reciprocal of m -- not the paper's arithmetic but that of the GPU's reciprocal-product
- * variant, kept here so that variant can be checked bit for bit.
+ * variant, kept here so that variant can be checked bit for bit. prec = 65 is the double
+ * decision with the slope formed as the double difference times the double reciprocal of m
+ * (within one ulp of the double quotient), the arithmetic of the GPU's default path.
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no -ffast-math).
  */
@@ -253,8 +255,9 @@ static ray_t walk(const float *D, const sector_t *S, int mode, long long t_or_p0
         double z = sample_z(D, S, u, fr, j);
         int visible;
         double th_rec;
-        if (prec == 64) {
-            double th = (z - h64) / (double)m;
+        if (prec == 64 || prec == 65) {
+            double dz = z - h64;
+            double th = prec == 64 ? dz / (double)m : dz * (1.0 / (double)m);
             visible = th > mx64;
             if (visible) mx64 = th;
             th_rec = th;
@@ -380,7 +383,7 @@ int oracle_sector_V(const float *dem, int rows, int cols, double dx, double h0, 
 {
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (k < 0 || k >= n || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
+    if (k < 0 || k >= n || (prec != 32 && prec != 33 && prec != 64 && prec != 65)) return ORC_EINVAL;
     sector_t S;
     memset(&S, 0, sizeof(S));
     if (sector_init(&S, k, n, rows, cols, dx, R) != ORC_OK) { sector_free(&S); return ORC_ENOMEM; }
@@ -417,7 +420,7 @@ int oracle_total(const float *dem, int rows, int cols, double dx, double h0, int
     long long evals = 0;
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (!out || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
+    if (!out || (prec != 32 && prec != 33 && prec != 64 && prec != 65)) return ORC_EINVAL;
     if (r0 < 0 || c0 < 0 || nr < 0 || nc < 0 || r0 + nr > rows || c0 + nc > cols) return ORC_EINVAL;
     sector_t *S = make_sectors(rows, cols, dx, n, R);
     if (!S) return ORC_ENOMEM;
@@ -472,7 +475,7 @@ int oracle_singular(const float *dem, int rows, int cols, double dx, double h0, 
 {
     int rc = check_args(dem, rows, cols, dx, h0, n, R);
     if (rc) return rc;
-    if (!out_area || (prec != 32 && prec != 33 && prec != 64)) return ORC_EINVAL;
+    if (!out_area || (prec != 32 && prec != 33 && prec != 64 && prec != 65)) return ORC_EINVAL;
     if (i0 < 0 || i0 >= rows || j0 < 0 || j0 >= cols) return ORC_EINVAL;
     sector_t *S = make_sectors(rows, cols, dx, n, R);
     if (!S) return ORC_ENOMEM;
@@ -529,7 +532,7 @@ int oracle_ray(const float *dem, int rows, int cols, double dx, double h0, int n
     if (out_cv) *out_cv = a.cv;
     if (out_U) *out_U = (uint32_t)a.U;
     if (out_e) *out_e = a.e;
-    if (out_h) *out_h = prec == 64 ? h64 : (double)h32;
+    if (out_h) *out_h = prec >= 64 ? h64 : (double)h32;
     sector_free(&S);
     return ORC_OK;
 }

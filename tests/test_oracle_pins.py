@@ -40,7 +40,7 @@ def test_golden_row5(orc):
         R = INF if case["max_dist"] == "inf" else float(case["max_dist"])
         tv = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], R)
         np.testing.assert_allclose(tv[0] / (math.pi / 2), case["tvs_over_pi_half"], rtol=1e-13)
-        for prec in (32, 33):
+        for prec in (32, 33, 65):
             tvp = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], R, prec=prec)
             np.testing.assert_allclose(tvp[0] / (math.pi / 2), case["tvs_over_pi_half"], rtol=1e-13)
 
@@ -49,7 +49,7 @@ def test_golden_grid5(orc):
     """Hand-derived 5x5 example at 0/45/90/135 deg: pins axis orientation, case transforms and 1/cos^2."""
     g = json.load(open(os.path.join(GOLD, "grid5.json")))
     dem = np.array(g["dem"], np.float32)
-    for prec in (64, 32, 33):
+    for prec in (64, 65, 32, 33):
         tv = orc.total(dem, g["spacing"], g["obs_height"], g["n_sectors"], INF, prec=prec)
         for i, j, v in g["cells_tvs_over_pi"]:
             assert tv[i, j] / math.pi == pytest.approx(v, rel=1e-13)
@@ -219,7 +219,7 @@ def test_n1_n2_equal_row_and_column_walks(orc, R):
 
 # ------------------------------------------------------------------ P5: singular == total at n = 4
 
-@pytest.mark.parametrize("prec", [64, 32, 33])
+@pytest.mark.parametrize("prec", [64, 65, 32, 33])
 def test_n4_singular_equals_total(orc, prec):
     """P5: at 0/45/90/135 deg every skew weight is 0, so the two skewed POVs a cell blends
     collapse to the cell itself and the total viewshed equals the singular one exactly."""
@@ -245,7 +245,7 @@ def test_singular_close_to_total_on_smooth_terrain(orc):
 
 # ------------------------------------------------------------------ P6: brute force per pair
 
-@pytest.mark.parametrize("prec", [64, 32, 33])
+@pytest.mark.parametrize("prec", [64, 65, 32, 33])
 def test_running_max_equals_brute_force(orc, prec):
     """P6: 'visible iff the slope beats the running maximum' equals the O(M^2) definition
     'visible iff every earlier slope is strictly smaller', and the ring sum follows from it."""
@@ -342,7 +342,7 @@ def test_skewed_samples_lie_on_straight_lines(orc, n):
 
 # ------------------------------------------------------------------ P8/P9: symmetries
 
-@pytest.mark.parametrize("prec", [32, 33])
+@pytest.mark.parametrize("prec", [32, 33, 64, 65])
 @pytest.mark.parametrize("n", [4, 7, 10])
 def test_mirror_pairs_agree_exactly(orc, n, prec):
     """P8: mirroring the grid left-right maps axis k to axis (n - k) mod n. For 0 < k, k != n/2
@@ -520,3 +520,30 @@ def test_reciprocal_slope_within_one_ulp_of_quotient(orc):
         tb = b["theta"].astype(np.float32)
         assert a["M"] == b["M"] > 10
         assert np.all(np.abs(ta.view(np.int32) - tb.view(np.int32)) <= 1)
+
+
+def test_double_reciprocal_slope_within_one_ulp_of_quotient(orc):
+    """prec 65 forms the double slope as the difference times the double reciprocal of m; on a
+    ray its slopes lie within one double ulp of prec 64's correctly rounded quotients (a float
+    reciprocal, or a float difference, would be off by about 2^29 ulps)."""
+    dem = fractal_dem(40, 8, 0.6, 900.0)
+    for k in (0, 3, 7):
+        a = orc.ray(dem, 10.0, 1.5, 12, INF, k, 0, 5, 2, 1, prec=64)
+        b = orc.ray(dem, 10.0, 1.5, 12, INF, k, 0, 5, 2, 1, prec=65)
+        assert a["M"] == b["M"] > 10
+        assert np.all(np.abs(a["theta"].view(np.int64) - b["theta"].view(np.int64)) <= 1)
+        assert np.any(a["theta"] != b["theta"])  # the two forms do differ somewhere
+
+
+def test_double_reciprocal_decisions_match_quotient(orc):
+    """Deciding in double with the reciprocal product agrees with the double quotient on every
+    POV-sector pair of a fractal grid (a one-ulp double difference almost never decides a tie)."""
+    dem = fractal_dem(64, 1, 0.6, 1500.0)
+    pairs = 0
+    for k in (0, 17, 45, 62, 90, 133, 170):
+        a = orc.sector_V(dem, 10.0, 1.5, 180, 640.0, k, prec=64)
+        b = orc.sector_V(dem, 10.0, 1.5, 180, 640.0, k, prec=65)
+        v = a["valid"].astype(bool)
+        pairs += int(v.sum())
+        assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["e"], b["e"])
+    assert pairs > 20000
