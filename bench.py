@@ -20,13 +20,16 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X: 256 CUs at a 2.4 GHz peak engine clock; the published FP32 vector peak, 157.3 TFLOP/s,
-# is 128 FP32 lane-operations per CU per clock with an FMA counted as 2 flops. Plain (non-packed)
+# MI355X: 256 CUs at a 2.4 GHz peak engine clock. The published FP32 vector peak, 157.3 TFLOP/s,
+# is 128 FP32 lane-operations per CU per clock with an FMA counted as 2 flops; plain (non-packed)
 # FP32 VALU instructions reach that issue rate on gfx950 (VALU counters of the sweep show more
-# than 64 lanes/clk/CU). One line-of-sight evaluation is 5 algorithmic operations: subtract,
-# divide, compare, max, conditional integer add; the peak counts each lane-operation once.
-CU, LANES, CLOCK_HZ = 256, 128, 2.4e9
-ALU_PEAK_OPS = CU * LANES * CLOCK_HZ          # 7.86e13 lane-ops/s = 157.3 TFLOP/s / 2
+# than 64 lanes/clk/CU). The FP64 vector peak, 78.6 TFLOP/s, is 64 FP64 lane-operations per CU
+# per clock. One line-of-sight evaluation is 5 algorithmic operations: subtract, divide, compare,
+# max, conditional integer add; the peak counts each lane-operation once, at the rate of the
+# precision the decision is taken in.
+CU, CLOCK_HZ = 256, 2.4e9
+ALU_PEAK_OPS_F32 = CU * 128 * CLOCK_HZ        # 7.86e13 lane-ops/s = 157.3 TFLOP/s / 2
+ALU_PEAK_OPS_F64 = CU * 64 * CLOCK_HZ         # 3.93e13 lane-ops/s = 78.6 TFLOP/s / 2
 OPS_PER_EVAL = 5
 HBM_PEAK_GBS = 8000.0
 
@@ -144,7 +147,9 @@ def main():
         log("non-finite output")
         sys.exit(1)
 
-    # dominant kernel: the sweep (ALU bound)
+    # dominant kernel: the sweep (ALU bound), priced at the peak of the decision's precision
+    f32 = bool(args.flags & tvs.FLAG_SLOPE_F32)
+    ALU_PEAK_OPS = ALU_PEAK_OPS_F32 if f32 else ALU_PEAK_OPS_F64
     avg_sweep_s = sweep_ms / 1e3 / max(sweep_n, 1)
     ops_per_launch = OPS_PER_EVAL * evals_done * args.steps / max(sweep_n, 1)
     achieved = ops_per_launch / avg_sweep_s if sweep_n else None
@@ -208,10 +213,11 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.flags & tvs.FLAG_SLOPE_F64 else "f32",
-        "slope": ("double quotient" if args.flags & tvs.FLAG_SLOPE_F64 else
-                  "correctly rounded float quotient" if args.flags & tvs.FLAG_SLOPE_EXACT else
-                  "float difference x float reciprocal"),
+        "dtype": "f32" if f32 else "f64",
+        "slope": (("correctly rounded float quotient" if args.flags & tvs.FLAG_SLOPE_EXACT else
+                   "float difference x float reciprocal") if f32 else
+                  "correctly rounded double quotient" if args.flags & (tvs.FLAG_SLOPE_F64 | tvs.FLAG_SLOPE_EXACT) else
+                  "double difference x double reciprocal"),
         "data": "synthetic",
         "config": {
             "workload": f"{args.workload}: {H}x{W} diamond-square DEM (seed {w['seed']}, roughness {w['roughness']}, "

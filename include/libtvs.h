@@ -22,7 +22,10 @@
  *            (the paper's own unbounded setting). A line of sight of sector s' stops at
  *            index distance m < rho = max_dist cos(s') / spacing and its last ring is
  *            clipped at rho.
- * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE.
+ * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE. A skewed row is held in the
+ *            LDS of one workgroup: with the default double elevations that caps the longer side
+ *            at about 19,000 (TVS_ERANGE beyond; TVS_FLAG_SLOPE_F32 rows take half the bytes
+ *            per sample and reach 32767).
  * Results    Areas in square metres, double.
  *
  * Errors: every call returns TVS_OK (0) or a negative status; on error the outputs are
@@ -45,7 +48,7 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 2
+#define TVS_ABI_VERSION 3
 
 enum tvs_status {
     TVS_OK = 0,
@@ -55,20 +58,26 @@ enum tvs_status {
     TVS_ERANGE = -4   /* grid side above 32767 */
 };
 
-/* Variant flags. The default, 0, decides visibility in float (the paper's kernels declare the
- * slope float, Alg. 7/8) with the slope formed as the float elevation difference times the float
- * reciprocal of the index distance, steps one lane per POV in the sweep, ends a group of 64 lines
- * of sight early once no remaining target can rise above any of their horizons (results are
- * those of the full walk: the bound uses only monotone roundings), and accumulates each cell in
- * double. */
-#define TVS_FLAG_SLOPE_F64 0x1u   /* visibility decided in double from double elevations */
+/* Variant flags. The default, 0, keeps the interpolated elevations in double and decides
+ * visibility in double, the slope formed as the elevation difference times the double reciprocal
+ * of the index distance (within one double ulp of the quotient). It steps one lane per POV in the
+ * sweep, and it ends a group of 64 lines of sight early once no remaining target can rise above any
+ * of their horizons. The results are those of the full walk, because the bound uses only monotone
+ * roundings. Each cell is accumulated in double.
+ * The paper's kernels declare their slopes float (Alg. 7/8); TVS_FLAG_SLOPE_F32 takes that
+ * precision. It flips the decision of about 4e-4 of the POV-sector pairs of a 2000 x 2000 grid
+ * with 1000-sample lines of sight, against about 1e-9 for the default. */
+#define TVS_FLAG_SLOPE_F64 0x1u   /* double decision, slope as the correctly rounded double quotient */
 #define TVS_FLAG_SWEEP_SCAN 0x2u  /* sweep with one lane per target and wavefront prefix-max */
 #define TVS_FLAG_ACC_KAHAN32 0x4u /* float Kahan-compensated per-cell accumulation */
-#define TVS_FLAG_SLOPE_EXACT 0x8u /* float slope as the correctly rounded quotient of difference
-                                     and distance (an IEEE float division) */
+#define TVS_FLAG_SLOPE_EXACT 0x8u /* slope as the correctly rounded quotient of difference and
+                                     distance in the decision's precision (an IEEE division) */
 #define TVS_FLAG_NO_PRUNE 0x10u   /* walk every target in range, as Alg. 8 does (same results) */
 #define TVS_FLAG_COUNT_EVALS 0x20u /* total viewshed only, needs `stats`: count the line-of-sight
                                       evaluations the sweep carries out into stats->sweep_evals_done */
+#define TVS_FLAG_SLOPE_F32 0x40u  /* float elevations and float decision (the paper's precision);
+                                     with TVS_FLAG_SLOPE_EXACT the float quotient. Excludes
+                                     TVS_FLAG_SLOPE_F64 */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for
@@ -129,7 +138,8 @@ int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double
                           double obs_height, int32_t n_sectors, double max_dist, double *d_out,
                           uint32_t flags, tvs_stats *stats, void *hip_stream);
 
-/* tvs_singular_viewshed_async with variant flags (TVS_FLAG_SLOPE_F64, TVS_FLAG_SLOPE_EXACT) and, when
+/* tvs_singular_viewshed_async with variant flags (TVS_FLAG_SLOPE_F64, TVS_FLAG_SLOPE_EXACT,
+ * TVS_FLAG_SLOPE_F32) and, when
  * d_ray_V is non-NULL, the per-line-of-sight ring sums: d_ray_V[2k] forward and [2k+1]
  * backward of sector k, packed as U | (e << 30) (U whole rings in index^2 units including
  * the POV ring, e in {0,1} clipped last ring of area rho^2 - K^2, K = ceil(rho) - 1). */
@@ -151,6 +161,12 @@ int tvs_sector_shape(int32_t rows, int32_t cols, int32_t n_sectors, int32_t sect
 int tvs_debug_sector_rays(const float *dem, int32_t rows, int32_t cols, double spacing,
                           double obs_height, int32_t n_sectors, double max_dist, int32_t sector,
                           uint32_t flags, uint32_t *out_V);
+
+/* tvs_debug_sector_rays on device memory: d_dem (rows*cols float) and d_out_V (nrows x ncols
+ * u32) are device pointers on the current HIP device; the work is enqueued on hip_stream. */
+int tvs_debug_sector_rays_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                                double obs_height, int32_t n_sectors, double max_dist, int32_t sector,
+                                uint32_t flags, uint32_t *d_out_V, void *hip_stream);
 
 /* Work of one total viewshed call, from the sector geometry alone: line-of-sight cell
  * evaluations (per skewed row of nt samples, 2 * sum_{q<nt} min(q, K)) and POV-sector pairs. */

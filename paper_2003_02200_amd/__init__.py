@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
-    "FLAG_COUNT_EVALS", "Stats",
+    "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "Stats",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -28,6 +28,7 @@ FLAG_ACC_KAHAN32 = 0x4
 FLAG_SLOPE_EXACT = 0x8
 FLAG_NO_PRUNE = 0x10
 FLAG_COUNT_EVALS = 0x20
+FLAG_SLOPE_F32 = 0x40
 
 _STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
 
@@ -73,10 +74,11 @@ def lib():
         L.tvs_singular_viewshed_ex.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, i32, u32, vp, vp, vp]
         L.tvs_sector_shape.argtypes = [i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.tvs_debug_sector_rays.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, u32, vp]
+        L.tvs_debug_sector_rays_async.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, u32, vp, vp]
         L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
-                     "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_los_evals"):
+                     "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -187,8 +189,26 @@ def sector_shape(rows: int, cols: int, n_sectors: int, sector: int):
 
 
 def debug_sector_rays(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float, sector: int,
-                      flags: int = 0) -> np.ndarray:
-    """Per-sector skewed viewshed (nrows x ncols u32, U | e << 30; 0xFFFFFFFF = no sample)."""
+                      flags: int = 0, stream=None):
+    """Per-sector skewed viewshed (nrows x ncols, U | e << 30; 0xFFFFFFFF = no sample).
+
+    A host numpy grid gives a numpy uint32 array (synchronous); a CUDA float32 tensor gives an
+    int32 tensor on its device holding the same bits, ordered on ``stream`` or the current stream.
+    """
+    if _is_torch_cuda(dem):
+        import torch
+
+        if dem.dtype != torch.float32 or dem.dim() != 2:
+            raise ValueError("device dem must be a 2-D float32 tensor")
+        d = dem.contiguous()
+        H, W = d.shape
+        nr, nc, _ = sector_shape(H, W, n_sectors, sector)
+        out = torch.empty((nr, nc), dtype=torch.int32, device=d.device)
+        with torch.cuda.device(d.device):
+            _check(lib().tvs_debug_sector_rays_async(C.c_void_p(d.data_ptr()), H, W, spacing, obs_height, n_sectors,
+                                                     max_dist, sector, flags, C.c_void_p(out.data_ptr()),
+                                                     _stream_handle(stream)))
+        return out
     a = _host_dem(dem)
     H, W = a.shape
     nr, nc, _ = sector_shape(H, W, n_sectors, sector)

@@ -118,8 +118,10 @@ int check_host_dem(const float *dem, int rows, int cols) {
 
 int check_flags(uint32_t flags, bool accumulation) {
     const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_NO_PRUNE |
-                           (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS : 0u);
+                           TVS_FLAG_SLOPE_F32 | (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
+    if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
     return TVS_OK;
 }
 
@@ -260,10 +262,10 @@ int lds_limit(int dev) {
 int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
               uint32_t flags, tvs_stats *stats, hipStream_t st, int debug_sector, uint32_t *d_debugV,
               int *debug_pitch) {
-    const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
-    const bool rcp = (flags & TVS_FLAG_SLOPE_EXACT) == 0;
+    const bool rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
     const bool prune = (flags & TVS_FLAG_NO_PRUNE) == 0;
     const bool count = (flags & TVS_FLAG_COUNT_EVALS) != 0;
     if (count && !stats) return fail(TVS_EINVAL, "TVS_FLAG_COUNT_EVALS needs a stats argument");
@@ -273,8 +275,9 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const int pitch = pitch_of(H, W);
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
     if (sweep_lds_bytes(std::max(H, W), f64) + 64 > (size_t)lds_limit(dev))  // + the kernels' static LDS
-        return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)",
-                    std::max(H, W), f64 ? "double" : "float", lds_limit(dev));
+        return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)%s",
+                    std::max(H, W), f64 ? "double" : "float", lds_limit(dev),
+                    f64 ? "; TVS_FLAG_SLOPE_F32 takes float rows" : "");
 
     std::vector<Sector> S;
     if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));
@@ -369,8 +372,8 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
 
 int run_singular(const float *d_dem, int H, int W, double dx, double h0, int n, double R, int pi, int pj,
                  uint32_t flags, double *d_area, uint32_t *d_rayV, hipStream_t st) {
-    const bool f64 = (flags & TVS_FLAG_SLOPE_F64) != 0;
-    const bool rcp = (flags & TVS_FLAG_SLOPE_EXACT) == 0;
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
+    const bool rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     pool_keep_memory(dev);
@@ -466,8 +469,10 @@ int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, dou
     if (rc) return rc;
     if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
         return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, rows, cols);
-    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT))
+    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F32))
         return fail(TVS_EINVAL, "unsupported flags 0x%x for the singular viewshed", flags);
+    if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
     return run_singular(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, flags,
                         d_area, d_ray_V, (hipStream_t)hip_stream);
 }
@@ -547,6 +552,20 @@ int tvs_debug_sector_rays(const float *dem, int32_t rows, int32_t cols, double s
     HIPCHK(hipStreamSynchronize(nullptr));
     HIPCHK(hipMemcpy(out_V, d_V.p, NV * sizeof(uint32_t), hipMemcpyDeviceToHost));
     return TVS_OK;
+}
+
+int tvs_debug_sector_rays_async(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                                int32_t n_sectors, double max_dist, int32_t sector, uint32_t flags, uint32_t *d_out_V,
+                                void *hip_stream) {
+    g_err[0] = 0;
+    if (!d_dem || !d_out_V) return fail(TVS_EINVAL, "null d_dem or d_out_V pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (sector < 0 || sector >= n_sectors) return fail(TVS_EINVAL, "sector %d outside [0, %d)", sector, n_sectors);
+    if (int rc2 = check_flags(flags, false)) return rc2;
+    int pitch = 0;
+    return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, nullptr, flags, nullptr,
+                     (hipStream_t)hip_stream, sector, d_out_V, &pitch);
 }
 
 int tvs_los_evals(int32_t rows, int32_t cols, double spacing, int32_t n_sectors, double max_dist, int64_t *out_evals,

@@ -20,12 +20,12 @@
 // and the singular viewshed (Alg. 1-3) as a ray scan: one wavefront per line of sight, lanes =
 // 64 consecutive targets, the horizon carried by a wavefront prefix-max.
 //
-// Floating point: the float path rounds the interpolated elevation to float, forms h = z + h0
-// and d = z - h, and the slope as d times the float reciprocal of m (default) or as the
-// correctly rounded quotient d / m (exact mode: reciprocal, one product and one FMA
-// correction, exact for every integer m in range); visibility is compared in float. The
-// double path forms the correctly rounded double quotient. Explicit _rn intrinsics keep the
-// compiler from contracting any step into an FMA.
+// Floating point: the default path keeps the interpolated elevation in double, forms h = z + h0
+// and d = z - h in double and the slope as d times the double reciprocal of m, and compares in
+// double. The float path rounds the interpolated elevation to float and does the same steps in
+// float. Either precision can instead form the correctly rounded quotient d / m (exact mode:
+// reciprocal, one product and one FMA correction, exact for every integer m in range).
+// Explicit _rn intrinsics keep the compiler from contracting any step into an FMA.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -53,7 +53,10 @@ __device__ __forceinline__ float slope_rcp(float d, float2 t) { return __fmul_rn
 template <bool RCP> __device__ __forceinline__ float slope(float d, float2 t) {
     return RCP ? slope_rcp(d, t) : slope_div(d, t);
 }
-template <bool RCP> __device__ __forceinline__ double slope(double d, double2 t) { return slope_div(d, t); }
+// Default double slope: the double difference times the double reciprocal of m.
+template <bool RCP> __device__ __forceinline__ double slope(double d, double2 t) {
+    return RCP ? __dmul_rn(d, t.y) : slope_div(d, t);
+}
 __device__ __forceinline__ float add_rn(float a, float b) { return __fadd_rn(a, b); }
 __device__ __forceinline__ double add_rn(double a, double b) { return __dadd_rn(a, b); }
 __device__ __forceinline__ float sub_rn(float a, float b) { return __fsub_rn(a, b); }
@@ -740,7 +743,7 @@ __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float
                 const Tz z = (Tz)z64;
                 const Tz dz = sub_rn(z, h);
                 if constexpr (sizeof(Tz) == 4) th = RCP ? __fmul_rn(dz, __fdiv_rn(1.0f, (float)m)) : __fdiv_rn(dz, (float)m);
-                else th = __ddiv_rn(dz, (double)m);
+                else th = RCP ? __dmul_rn(dz, __ddiv_rn(1.0, (double)m)) : __ddiv_rn(dz, (double)m);
             }
         }
         // existence is monotone along the line of sight, so the valid lanes form a prefix
@@ -827,8 +830,9 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
     const size_t lds = sweep_lds_bytes(maxWx, f64);
     constexpr int NW = SWEEP_WAVES;
     if (f64) {
-        auto f = scan ? k_sweep_scan<double, NW, false>
-                      : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
+        auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
+                 : rcp ? (prune ? k_sweep<double, NW, true, true> : k_sweep<double, NW, true, false>)
+                       : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
         return sweep_go<double>(f, grid, lds, st, a, skw, V, tab64, work);
     }
     auto f = scan ? (rcp ? k_sweep_scan<float, NW, true> : k_sweep_scan<float, NW, false>)
@@ -848,7 +852,8 @@ hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, f
 hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, bool rcp,
                            hipStream_t st) {
     const int blocks = (2 * a.nsec + 3) / 4;
-    if (f64) k_singular<double, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    if (f64 && rcp) k_singular<double, true><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    else if (f64) k_singular<double, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
     else if (rcp) k_singular<float, true><<<blocks, 256, 0, st>>>(a, dem, rayV);
     else k_singular<float, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
     return hipGetLastError();

@@ -2,10 +2,11 @@
 
 Bar (from the method's arithmetic):
 * per-sector skewed viewshed (integer ring sums U and clipped-ring counts e): bit-exact against
-  the oracle taking the same decisions in the same precision -- float for the default path
-  (the paper's single-precision kernels; slope = difference times float reciprocal, oracle
-  prec=33) and for TVS_FLAG_SLOPE_EXACT (correctly rounded float quotient, prec=32), double for
-  TVS_FLAG_SLOPE_F64 (prec=64);
+  the oracle taking the same decisions in the same precision -- double with the slope as the
+  difference times the double reciprocal for the default path (oracle prec=65), the double
+  quotient for TVS_FLAG_SLOPE_F64 or TVS_FLAG_SLOPE_EXACT (prec=64), and the paper's float
+  kernels for TVS_FLAG_SLOPE_F32 (difference times float reciprocal, prec=33; with
+  TVS_FLAG_SLOPE_EXACT the correctly rounded float quotient, prec=32);
 * total viewshed map: equal to that oracle up to double summation order (rtol 1e-12);
 * against the all-double oracle: per-cell relative error <= 1e-4 on cells without a horizon
   flip, horizon flips (POV-sector pairs whose U or e differ) <= 1e-5 of all pairs.
@@ -20,7 +21,10 @@ from synth import cone, flat, fractal_dem, plane, workload_dem, WORKLOADS
 
 pytestmark = pytest.mark.gpu
 INF = math.inf
-P_DEFAULT, P_EXACT, P_DOUBLE = 33, 32, 64
+P_DEFAULT, P_DOUBLE, P_F32, P_F32_EXACT = 65, 64, 33, 32
+# (flags, oracle precision) of every decision mode: default, double quotient, float, float quotient
+F64, EXACT, F32 = 0x1, 0x8, 0x40
+MODES = [(0, P_DEFAULT), (F64, P_DOUBLE), (F32, P_F32), (F32 | EXACT, P_F32_EXACT)]
 
 
 def note(msg):
@@ -83,10 +87,10 @@ def _sectors(n):
 
 
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
-def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
+def test_sector_rays_bitexact_default(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind)
     for k in _sectors(n):
-        note(f"sector_rays float H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        note(f"sector_rays default H={H} W={W} n={n} R={R} k={k} kind={kind}")
         g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k)
         o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_DEFAULT)
         assert g.shape == o["U"].shape
@@ -94,15 +98,26 @@ def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
         assert bad.size == 0, f"k={k}: {len(bad)} samples differ, first {bad[:3].tolist()}"
 
 
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
+def test_sector_rays_bitexact_float(tvs, orc, H, W, n, R, kind):
+    """TVS_FLAG_SLOPE_F32 (the paper's float kernels) against the oracle's float mode."""
+    dem = _dem(H, W, kind, seed=4)
+    for k in _sectors(n):
+        note(f"sector_rays float H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=F32)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_F32)
+        assert np.array_equal(g, packed(o)), f"k={k}"
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[::2])
-def test_sector_rays_bitexact_exact_division(tvs, orc, H, W, n, R, kind):
-    """TVS_FLAG_SLOPE_EXACT (correctly rounded float quotient) against the oracle's float
-    division mode."""
+def test_sector_rays_bitexact_float_quotient(tvs, orc, H, W, n, R, kind):
+    """TVS_FLAG_SLOPE_F32 | TVS_FLAG_SLOPE_EXACT (correctly rounded float quotient) against the
+    oracle's float division mode."""
     dem = _dem(H, W, kind, seed=6)
     for k in _sectors(n):
-        note(f"sector_rays exact H={H} W={W} n={n} R={R} k={k} kind={kind}")
-        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_EXACT)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_EXACT)
+        note(f"sector_rays float quotient H={H} W={W} n={n} R={R} k={k} kind={kind}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=F32 | EXACT)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_F32_EXACT)
         assert np.array_equal(g, packed(o)), f"k={k}"
 
 
@@ -119,7 +134,7 @@ def test_sector_rays_signed_zeros_and_ties(tvs, orc, h0):
     for n, R in ((8, INF), (12, 400.0)):
         for k in range(n):
             note(f"signed zeros h0={h0} n={n} R={R} k={k}")
-            for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT)):
+            for flags, prec in MODES:
                 g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags)
                 o = orc.sector_V(dem, 10.0, h0, n, R, k, prec=prec)
                 assert np.array_equal(g, packed(o)), f"n={n} k={k} flags={flags}"
@@ -130,9 +145,10 @@ def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind, seed=5)
     for k in _sectors(n):
         note(f"sector_rays double H={H} W={W} n={n} R={R} k={k} kind={kind}")
-        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SLOPE_F64)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=64)
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=F64)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_DOUBLE)
         assert np.array_equal(g, packed(o)), f"k={k}"
+        assert np.array_equal(tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=EXACT), g)
 
 
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[1::3])
@@ -140,13 +156,11 @@ def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
     """The lane-per-target sweep (wavefront prefix-max horizon) gives the same integers."""
     dem = _dem(H, W, kind, seed=8)
     for k in _sectors(n)[:6]:
-        note(f"sector_rays scan H={H} W={W} n={n} R={R} k={k}")
-        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_DEFAULT)
-        assert np.array_equal(g, packed(o)), f"k={k}"
-        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN | tvs.FLAG_SLOPE_EXACT)
-        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=P_EXACT)
-        assert np.array_equal(g, packed(o)), f"k={k} exact"
+        for flags, prec in MODES:
+            note(f"sector_rays scan H={H} W={W} n={n} R={R} k={k} flags={flags}")
+            g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_SWEEP_SCAN | flags)
+            o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=prec)
+            assert np.array_equal(g, packed(o)), f"k={k} flags={flags}"
 
 
 def _walled(H, W, seed):
@@ -182,13 +196,13 @@ def _exit_dem(H, W, kind, seed):
 @pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES)
 def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
     """The sweep's early exit changes no ring sum: pruned and full walks agree bit for bit with
-    each other and with the oracle, in all three slope precisions, for observers above and
-    below ground."""
+    each other and with the oracle, in every decision mode, for observers above and below
+    ground."""
     dem = _exit_dem(H, W, kind, seed=H + W)
     for h0 in (1.5, -3.0, 40.0):
         for k in range(n):
             note(f"early exit H={H} W={W} n={n} R={R} kind={kind} h0={h0} k={k}")
-            for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT), (tvs.FLAG_SLOPE_F64, P_DOUBLE)):
+            for flags, prec in MODES:
                 g = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags)
                 full = tvs.debug_sector_rays(dem, 10.0, h0, n, R, k, flags=flags | tvs.FLAG_NO_PRUNE)
                 assert np.array_equal(g, full), f"k={k} flags={flags}: pruned and full walks differ"
@@ -218,15 +232,10 @@ def test_evaluation_counts(tvs, H, W, n, R, kind):
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
 def test_total_small(tvs, orc, H, W, n, R, kind):
     dem = _dem(H, W, kind, seed=11)
-    note(f"total H={H} W={W} n={n} R={R} kind={kind}")
-    g = tvs.total_viewshed(dem, 10.0, 1.5, n, R)
-    np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, R, prec=P_DEFAULT), rtol=1e-12, atol=0)
-    note(f"total exact H={H} W={W} n={n} R={R} kind={kind}")
-    g32 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_EXACT)
-    np.testing.assert_allclose(g32, orc.total(dem, 10.0, 1.5, n, R, prec=P_EXACT), rtol=1e-12, atol=0)
-    note(f"total f64 H={H} W={W} n={n} R={R} kind={kind}")
-    g64 = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SLOPE_F64)
-    np.testing.assert_allclose(g64, orc.total(dem, 10.0, 1.5, n, R, prec=P_DOUBLE), rtol=1e-12, atol=0)
+    for flags, prec in MODES:
+        note(f"total H={H} W={W} n={n} R={R} kind={kind} flags={flags}")
+        g = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=flags)
+        np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, R, prec=prec), rtol=1e-12, atol=0)
 
 
 def test_flat_full_disc_on_gpu(tvs):
@@ -246,6 +255,8 @@ def test_kahan_float_accumulation(tvs, orc):
     g = tvs.total_viewshed(dem, 10.0, 1.5, 60, 500.0, flags=tvs.FLAG_ACC_KAHAN32)
     o = orc.total(dem, 10.0, 1.5, 60, 500.0, prec=P_DEFAULT)
     np.testing.assert_allclose(g, o, rtol=2e-6)
+    g = tvs.total_viewshed(dem, 10.0, 1.5, 60, 500.0, flags=tvs.FLAG_ACC_KAHAN32 | F32)
+    np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, 60, 500.0, prec=P_F32), rtol=2e-6)
 
 
 def test_async_torch_stream_and_stats(tvs):
@@ -273,15 +284,12 @@ def test_singular(tvs, orc, H, W, n, R, pov):
     dem = fractal_dem(max(H, W), 17, 0.6, 600.0)[:H, :W].copy()
     i0, j0 = pov
     note(f"singular H={H} W={W} n={n} R={R} pov={pov}")
-    for flags, prec in ((0, P_DEFAULT), (tvs.FLAG_SLOPE_EXACT, P_EXACT)):
+    for flags, prec in MODES + [(EXACT, P_DOUBLE)]:
         area, rays = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, flags=flags, rays=True)
         o = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=prec)
         want = o["U"].astype(np.uint32) | (o["e"].astype(np.uint32) << np.uint32(30))
         assert np.array_equal(rays, want), flags
         assert area == pytest.approx(o["area"], rel=1e-12)
-    area64 = tvs.singular_viewshed(dem, 10.0, 1.5, n, R, i0, j0, flags=tvs.FLAG_SLOPE_F64)
-    o64 = orc.singular(dem, 10.0, 1.5, n, R, i0, j0, prec=64)
-    assert area64 == pytest.approx(o64["area"], rel=1e-12)
 
 
 def test_singular_cone_shadow(tvs):
@@ -292,10 +300,10 @@ def test_singular_cone_shadow(tvs):
     assert rays[2] == 51 ** 2
 
 
-def _flip_stats(tvs, orc, dem, dx, h0, n, R, sectors):
+def _flip_stats(tvs, orc, dem, dx, h0, n, R, sectors, flags=0):
     flips = pairs = 0
     for k in sectors:
-        g = tvs.debug_sector_rays(dem, dx, h0, n, R, k)
+        g = tvs.debug_sector_rays(dem, dx, h0, n, R, k, flags=flags)
         o = orc.sector_V(dem, dx, h0, n, R, k, prec=64)
         p = packed(o)
         v = o["valid"].astype(bool)
@@ -314,15 +322,17 @@ def test_workload_128_full_map(tvs, orc):
     g = tvs.total_viewshed(dem, *args)
     np.testing.assert_allclose(g, orc.total(dem, *args, prec=P_DEFAULT), rtol=1e-12)
     o64 = orc.total(dem, *args, prec=64)
-    note("workload tvs128 flips")
-    flips, pairs = _flip_stats(tvs, orc, dem, *args, range(w["n_sectors"]))
-    rel = np.abs(g - o64) / o64
-    print(f"tvs128: pairs={pairs} flips={flips} rate={flips / pairs:.3g} max_rel={rel.max():.3g} "
-          f"cells>1e-4={int((rel > 1e-4).sum())}", flush=True)
-    assert flips / pairs <= 1e-5
-    # cells off by more than rounding are exactly the cells fed by a flipped pair: at most 2 per flip
-    assert int((rel > 1e-10).sum()) <= 2 * flips
-    assert np.median(rel) < 1e-12
+    for name, flags in (("default", 0), ("float", F32)):
+        note(f"workload tvs128 flips {name}")
+        m = g if flags == 0 else tvs.total_viewshed(dem, *args, flags=flags)
+        flips, pairs = _flip_stats(tvs, orc, dem, *args, range(w["n_sectors"]), flags=flags)
+        rel = np.abs(m - o64) / o64
+        print(f"tvs128 {name}: pairs={pairs} flips={flips} rate={flips / pairs:.3g} max_rel={rel.max():.3g} "
+              f"cells>1e-4={int((rel > 1e-4).sum())}", flush=True)
+        assert flips / pairs <= 1e-5
+        # cells off by more than rounding are exactly the cells fed by a flipped pair: at most 2 per flip
+        assert int((rel > 1e-10).sum()) <= 2 * flips
+        assert np.median(rel) < 1e-12
 
 
 def test_workload_2000_sampled(tvs, orc):
@@ -351,10 +361,135 @@ def test_workload_2000_sampled(tvs, orc):
     worst32 = 0.0
     worst64 = 0.0
     for (i, j) in cells:
-        o32 = orc.total(dem, *args, prec=P_DEFAULT, window=(i, j, 1, 1))[0, 0]
+        o32 = orc.total(dem, *args, prec=P_DEFAULT, window=(i, j, 1, 1))[0, 0]  # same decisions
         o64 = orc.total(dem, *args, prec=64, window=(i, j, 1, 1))[0, 0]
         worst32 = max(worst32, abs(g[i, j] - o32) / o32)
         worst64 = max(worst64, abs(g[i, j] - o64) / o64)
-    print(f"tvs2000 sampled cells={len(cells)} max_rel_vs_f32={worst32:.3g} max_rel_vs_f64={worst64:.3g}", flush=True)
+    print(f"tvs2000 sampled cells={len(cells)} max_rel_vs_same_precision={worst32:.3g} "
+          f"max_rel_vs_double_quotient={worst64:.3g}", flush=True)
     assert worst32 <= 1e-12
-    assert worst64 <= 1e-2
+    assert worst64 <= 1e-4
+
+
+def _fed_cells(info, ri, j, H, W):
+    """Grid cells whose back-projection (Alg. 9) reads the skewed samples (t0 + ri, j) of a sector:
+    base-frame cell (t + d_j, j) with weight 1 - r_j and, when r_j > 0, (t + d_j + 1, j) with
+    weight r_j, mapped back through the sector's frame transform."""
+    d, r = info["d"][j], info["r"][j]
+    t = info["t0"] + ri
+    p = np.concatenate([t + d, (t + d + 1)[r > 0]])
+    q = np.concatenate([j, j[r > 0]])
+    keep = (p >= 0) & (p < info["Hx"])
+    p, q = p[keep], q[keep]
+    kase = info["case"]
+    if kase == 0:
+        return p, q
+    if kase == 1:
+        return q, p
+    if kase == 2:
+        return q, W - 1 - p
+    return p, W - 1 - q
+
+
+def _flip_scan(tvs, orc, d, args, flags_a, flags_b):
+    """Horizon flips between two GPU variants over every POV-sector pair (compared on the device),
+    and the cells they feed."""
+    import torch
+
+    H, W = d.shape
+    spacing, h0, n, R = args
+    fed = np.zeros((H, W), bool)
+    flips = pairs = 0
+    for k in range(n):
+        a = tvs.debug_sector_rays(d, spacing, h0, n, R, k, flags=flags_a)
+        b = tvs.debug_sector_rays(d, spacing, h0, n, R, k, flags=flags_b)
+        va = a != -1
+        assert torch.equal(va, b != -1), f"k={k}: sample sets differ"
+        diff = (a != b) & va
+        pairs += int(va.sum())
+        nf = int(diff.sum())
+        if nf:
+            flips += nf
+            ij = diff.nonzero().cpu().numpy()
+            i, j = _fed_cells(orc.sector_info(H, W, spacing, n, R, k), ij[:, 0], ij[:, 1], H, W)
+            fed[i, j] = True
+    torch.cuda.synchronize()
+    return flips, pairs, fed
+
+
+def test_workload_2000_crop_against_double_oracle(tvs, orc):
+    """The 2000 x 2000, 180-sector workload against the double oracle on the 256 x 256 centre crop
+    (R23), with horizon flips counted over all 7.2e8 POV-sector pairs against the GPU double
+    variant (R22), which itself must equal the oracle on the crop."""
+    import torch
+
+    w = WORKLOADS["tvs2000"]
+    dem = workload_dem("tvs2000")
+    H, W = dem.shape
+    args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    d = torch.from_numpy(dem).cuda()
+    note("tvs2000 maps: default, float, double quotient")
+    g = tvs.total_viewshed(d, *args).cpu().numpy()
+    gx = tvs.total_viewshed(d, *args, flags=F32).cpu().numpy()
+    g64 = tvs.total_viewshed(d, *args, flags=F64).cpu().numpy()
+    note("tvs2000 flips: default vs double quotient, float vs double quotient")
+    flips, pairs, fed = _flip_scan(tvs, orc, d, args, 0, F64)
+    flips_x, _, fed_x = _flip_scan(tvs, orc, d, args, F32, F64)
+    assert pairs == tvs.los_evals(H, W, w["spacing"], w["n_sectors"], w["max_dist"])[1]
+    c = (H - 256) // 2
+    note("tvs2000 crop: double oracle on 256 x 256 cells")
+    o64 = orc.total(dem, *args, prec=64, window=(c, c, 256, 256))
+    sl = (slice(c, c + 256), slice(c, c + 256))
+    np.testing.assert_allclose(g64[sl], o64, rtol=1e-12)
+    for name, m, fl, fd in (("default", g, flips, fed), ("float", gx, flips_x, fed_x)):
+        rel = np.abs(m[sl] - o64) / o64
+        clean = ~fd[sl]
+        rel_all = np.abs(m - g64) / g64
+        print(f"tvs2000 {name}: flips {fl} of {pairs} ({fl / pairs:.2e}); crop max rel {rel.max():.3g}, "
+              f"flip-free crop cells max rel {rel[clean].max():.3g}, crop cells fed by flips {int((~clean).sum())}; "
+              f"whole map: cells fed by flips {int(fd.sum())}, max rel {rel_all.max():.3g}, "
+              f"flip-free max rel {rel_all[~fd].max():.3g}", flush=True)
+        # the default meets the bound; the paper's float decision is reported (about 4e-4)
+        assert fl / pairs <= (1e-5 if name == "default" else 1e-3)
+        if name == "default":
+            assert rel.max() <= 1e-4
+        assert rel[clean].max() <= 1e-4
+        assert rel_all[~fd].max() <= 1e-10
+
+
+def test_workload_4000_precision_study(tvs, orc):
+    """The 4000 x 4000, 5 m, 360-sector workload: float sweep with double accumulation (default),
+    with float Kahan accumulation, with the exact float quotient, and the all-double variant; flips
+    of each float variant against the double one over every pair, per-cell errors over the whole
+    map against the double variant and on the 128 x 128 centre crop against the double oracle."""
+    import torch
+
+    w = WORKLOADS["tvs4000"]
+    dem = workload_dem("tvs4000")
+    H, W = dem.shape
+    args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    d = torch.from_numpy(dem).cuda()
+    maps = {}
+    for name, fl in (("double quotient", F64), ("default", 0), ("float", F32),
+                     ("float, kahan32", F32 | tvs.FLAG_ACC_KAHAN32), ("default, kahan32", tvs.FLAG_ACC_KAHAN32)):
+        note(f"tvs4000 map {name}")
+        maps[name] = tvs.total_viewshed(d, *args, flags=fl).cpu().numpy()
+    note("tvs4000 flips")
+    flips, pairs, fed = _flip_scan(tvs, orc, d, args, 0, F64)
+    flips_f, _, fed_f = _flip_scan(tvs, orc, d, args, F32, F64)
+    c = (H - 128) // 2
+    note("tvs4000 crop: double oracle on 128 x 128 cells")
+    o64 = orc.total(dem, *args, prec=64, window=(c, c, 128, 128))
+    sl = (slice(c, c + 128), slice(c, c + 128))
+    g64 = maps["double quotient"]
+    np.testing.assert_allclose(g64[sl], o64, rtol=1e-12)
+    for name, fd, fl in (("default", fed, flips), ("default, kahan32", fed, flips), ("float", fed_f, flips_f),
+                         ("float, kahan32", fed_f, flips_f)):
+        m = maps[name]
+        rel = np.abs(m - g64) / g64
+        relc = np.abs(m[sl] - o64) / o64
+        print(f"tvs4000 {name}: flips {fl} of {pairs} ({fl / pairs:.2e}), cells fed by flips {int(fd.sum())}; "
+              f"whole map max rel {rel.max():.3g}, flip-free max rel {rel[~fd].max():.3g}, "
+              f"p99 rel {np.quantile(rel, 0.99):.3g}; crop vs oracle max rel {relc.max():.3g}", flush=True)
+        assert rel[~fd].max() <= (1e-5 if "kahan32" in name else 1e-10)
+        assert fl / pairs <= (1e-5 if name.startswith("default") else 1e-2)
