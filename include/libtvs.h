@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 3
+#define TVS_ABI_VERSION 4
 
 enum tvs_status {
     TVS_OK = 0,
@@ -78,6 +78,9 @@ enum tvs_status {
 #define TVS_FLAG_SLOPE_F32 0x40u  /* float elevations and float decision (the paper's precision);
                                      with TVS_FLAG_SLOPE_EXACT the float quotient. Excludes
                                      TVS_FLAG_SLOPE_F64 */
+#define TVS_FLAG_AUTOTUNE 0x80u   /* batches only: time the candidate launch shapes on a sample of
+                                     the batch before building it and keep the fastest for batches
+                                     of the same size class (process-wide) */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for
@@ -147,6 +150,59 @@ int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, dou
                              double obs_height, int32_t n_sectors, double max_dist,
                              int32_t pov_row, int32_t pov_col, uint32_t flags, double *d_area,
                              uint32_t *d_ray_V, void *hip_stream);
+
+/* ---- Batches of independent tiles (uneven sizes) -------------------------------------------
+ * Every tile is an independent total viewshed (tvs_total_viewshed_async semantics) with its own
+ * size, spacing, observer height and max distance; all tiles share n_sectors. */
+typedef struct tvs_tile {
+    const float *d_dem;  /* device, rows*cols float32, row-major */
+    double *d_out;       /* device, rows*cols float64: the tile's total viewshed, m^2 */
+    int32_t rows, cols;
+    double spacing, obs_height, max_dist;
+} tvs_tile;
+
+typedef struct tvs_batch tvs_batch; /* opaque plan of a batch, owned by the caller */
+
+typedef struct tvs_batch_info {
+    int32_t tiles;
+    int32_t chunks;           /* sector groups, each one sweep and one back-projection launch */
+    int32_t kernel_launches;  /* kernels in the captured graph */
+    int32_t waves_per_group;  /* launch shape of the persistent sweep */
+    int32_t groups;           /* workgroups of the persistent sweep */
+    int32_t tuned;            /* 1 if the shape came from timing candidates */
+    int64_t los_evals;        /* closed-form line-of-sight evaluations of one pass */
+    int64_t pov_sector_pairs;
+    int64_t sweep_evals_done; /* evaluations carried out by the last completed pass
+                                 (TVS_FLAG_COUNT_EVALS), else 0 */
+    int64_t scratch_bytes;    /* device memory owned by the batch */
+    double tune_ms;           /* time spent timing candidates at creation */
+} tvs_batch_info;
+
+/* Plans a batch: validates every tile, groups the sectors into chunks within the scratch budget,
+ * uploads the work lists and captures one pass (per chunk: one persistent fused relocate + sweep
+ * launch over every (tile, sector, skewed row) item, then one back-projection launch over every
+ * tile) into a HIP graph. The DEM and output buffers are bound to the batch: they must stay
+ * allocated and in place until tvs_batch_destroy. Flags: TVS_FLAG_SLOPE_F32, TVS_FLAG_SLOPE_F64,
+ * TVS_FLAG_SLOPE_EXACT, TVS_FLAG_COUNT_EVALS, TVS_FLAG_AUTOTUNE. Runs on the current HIP device
+ * (synchronously at creation). Section 4.1 steps 1a-1d applied to every tile; the batching,
+ * fusion and graph are this library's, not the paper's. */
+int tvs_batch_create(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,
+                     tvs_batch **out_batch);
+
+/* Enqueues one pass over every tile on hip_stream (a graph launch); outputs are complete when
+ * the stream reaches that point. Passes on one batch must not overlap. */
+int tvs_batch_run(tvs_batch *batch, void *hip_stream);
+
+/* Plan, launch shape and counts of a batch (sweep_evals_done needs the last pass finished). */
+int tvs_batch_get_info(const tvs_batch *batch, tvs_batch_info *info);
+
+/* Releases the batch's graph and device memory (waits for its work). NULL is ignored. */
+int tvs_batch_destroy(tvs_batch *batch);
+
+/* The plain per-tile loop the batch is measured against: tvs_total_viewshed_ex on every tile in
+ * turn on hip_stream (flags as there). */
+int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,
+                             void *hip_stream);
 
 /* Shape of the skewed grid of sector `sector` (Section 4.1, Fig. 4b: one row per line of
  * sight): rows t = t0 .. t0 + nrows - 1, columns 0 .. ncols - 1 of the 0..45 deg base frame. */

@@ -16,7 +16,8 @@ import numpy as np
 __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
-    "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "Stats",
+    "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "Stats", "Batch", "BatchInfo",
+    "total_viewshed_tiles",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -29,6 +30,7 @@ FLAG_SLOPE_EXACT = 0x8
 FLAG_NO_PRUNE = 0x10
 FLAG_COUNT_EVALS = 0x20
 FLAG_SLOPE_F32 = 0x40
+FLAG_AUTOTUNE = 0x80
 
 _STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
 
@@ -47,6 +49,21 @@ class Stats(C.Structure):
         ("reloc_bytes", C.c_int64), ("sweep_bytes", C.c_int64), ("scratch_bytes", C.c_int64),
         ("sweep_evals_done", C.c_int64),
     ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Tile(C.Structure):
+    _fields_ = [("d_dem", C.c_void_p), ("d_out", C.c_void_p), ("rows", C.c_int32), ("cols", C.c_int32),
+                ("spacing", C.c_double), ("obs_height", C.c_double), ("max_dist", C.c_double)]
+
+
+class BatchInfo(C.Structure):
+    _fields_ = [("tiles", C.c_int32), ("chunks", C.c_int32), ("kernel_launches", C.c_int32),
+                ("waves_per_group", C.c_int32), ("groups", C.c_int32), ("tuned", C.c_int32),
+                ("los_evals", C.c_int64), ("pov_sector_pairs", C.c_int64), ("sweep_evals_done", C.c_int64),
+                ("scratch_bytes", C.c_int64), ("tune_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -75,10 +92,17 @@ def lib():
         L.tvs_sector_shape.argtypes = [i32, i32, i32, i32, C.POINTER(i32), C.POINTER(i32), C.POINTER(i32)]
         L.tvs_debug_sector_rays.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, u32, vp]
         L.tvs_debug_sector_rays_async.argtypes = [vp, i32, i32, f64, f64, i32, f64, i32, u32, vp, vp]
+        L.tvs_batch_create.argtypes = [C.POINTER(Tile), i32, i32, u32, C.POINTER(C.c_void_p)]
+        L.tvs_batch_run.argtypes = [vp, vp]
+        L.tvs_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
+        L.tvs_batch_destroy.argtypes = [vp]
+        L.tvs_total_viewshed_tiles.argtypes = [C.POINTER(Tile), i32, i32, u32, vp]
         L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
-                     "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals"):
+                     "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals",
+                     "tvs_batch_create", "tvs_batch_run", "tvs_batch_get_info", "tvs_batch_destroy",
+                     "tvs_total_viewshed_tiles"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -222,3 +246,57 @@ def los_evals(rows: int, cols: int, spacing: float, n_sectors: int, max_dist: fl
     ev, pr = C.c_int64(), C.c_int64()
     _check(lib().tvs_los_evals(rows, cols, spacing, n_sectors, max_dist, C.byref(ev), C.byref(pr)))
     return ev.value, pr.value
+
+
+def _tiles(tiles):
+    """(dem, out, spacing, obs_height, max_dist) device tensors and scalars -> Tile array (the
+    tensors must outlive every use of the array)."""
+    import torch
+
+    arr = (Tile * len(tiles))()
+    for x, (dem, out, spacing, h0, R) in enumerate(tiles):
+        if not (_is_torch_cuda(dem) and dem.dtype == torch.float32 and dem.dim() == 2 and dem.is_contiguous()):
+            raise ValueError(f"tile {x}: dem must be a contiguous 2-D float32 CUDA tensor")
+        if not (_is_torch_cuda(out) and out.dtype == torch.float64 and out.shape == dem.shape and out.is_contiguous()):
+            raise ValueError(f"tile {x}: out must be a contiguous float64 CUDA tensor of the dem's shape")
+        arr[x] = Tile(dem.data_ptr(), out.data_ptr(), dem.shape[0], dem.shape[1], spacing, h0, R)
+    return arr
+
+
+class Batch:
+    """A planned batch of independent tiles (tvs_batch_create); ``run`` replays its captured
+    graph on a stream. ``tiles`` is a list of (dem, out, spacing, obs_height, max_dist) with
+    device tensors that must stay alive (and in place) until ``close``."""
+
+    def __init__(self, tiles, n_sectors: int, flags: int = 0):
+        self._keep = [(t[0], t[1]) for t in tiles]
+        arr = _tiles(tiles)
+        h = C.c_void_p()
+        _check(lib().tvs_batch_create(arr, len(tiles), n_sectors, flags, C.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        _check(lib().tvs_batch_run(self._h, _stream_handle(stream)))
+
+    def info(self) -> BatchInfo:
+        inf = BatchInfo()
+        _check(lib().tvs_batch_get_info(self._h, C.byref(inf)))
+        return inf
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tvs_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def total_viewshed_tiles(tiles, n_sectors: int, flags: int = 0, stream=None):
+    """The plain per-tile loop (tvs_total_viewshed_tiles) over (dem, out, spacing, obs_height,
+    max_dist) device tiles, enqueued on ``stream`` or the current stream."""
+    arr = _tiles(tiles)
+    _check(lib().tvs_total_viewshed_tiles(arr, len(tiles), n_sectors, flags, _stream_handle(stream)))

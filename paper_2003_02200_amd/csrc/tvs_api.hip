@@ -17,10 +17,12 @@
 #include "../../include/libtvs.h"
 #include "tvs_geom.h"
 #include "tvs_internal.h"
+#include "tvs_host.h"
 
 using namespace tvs;
 
-namespace {
+namespace tvs {
+namespace host {
 
 thread_local char g_err[512] = "";
 
@@ -31,23 +33,6 @@ int fail(int code, const char *fmt, ...) {
     va_end(ap);
     return code;
 }
-
-#define HIPCHK(call)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (call);                                                               \
-        if (e_ != hipSuccess) return fail(TVS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
-
-// One sector of the plan (host side).
-struct Sector {
-    int kase, Hx, Wx;
-    double T;      // tan s'
-    double rho;    // max_dist cos s' / spacing
-    int K;         // last target index in range (TVS_K_UNBOUNDED when max_dist never binds)
-    double scale;  // (pi / 2n) spacing^2 / cos^2 s'
-    double clip;   // rho^2 - K^2
-    int t0, nrows;
-};
 
 // Sector k of n (Section 3.1 axes; base-frame cases of the kernels' 0..45 deg range).
 Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
@@ -92,7 +77,6 @@ Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
 // Elevations and the observer height must be finite, and either 0 or at least 2^-60 m in
 // magnitude. The second rule keeps every quantity of the sweep a multiple of 2^-83, so no slope
 // underflows to a signed zero (the kernels read strict comparisons from sign bits).
-const double TVS_MIN_MAGNITUDE = 0x1p-60;
 
 bool magnitude_ok(double v) { return v == 0.0 || fabs(v) >= TVS_MIN_MAGNITUDE; }
 
@@ -150,6 +134,33 @@ size_t scratch_budget() {
     if (hipMemGetInfo(&freeb, &total) != hipSuccess) return (size_t)4 << 30;
     return std::min(freeb / 2, (size_t)16 << 30);
 }
+
+void pool_keep_memory(int dev) {
+    static bool done[64] = {false};
+    if (dev < 0 || dev >= 64 || done[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    done[dev] = true;
+}
+
+int lds_limit(int dev) {
+    int v = 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
+        v = 65536;
+        (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    }
+    return v;
+}
+
+}  // namespace host
+}  // namespace tvs
+
+using namespace tvs::host;
+
+namespace {
 
 // Groups of consecutive sectors: at most TVS_CHUNK each, scratch within the budget.
 struct Chunk {
@@ -236,26 +247,6 @@ struct Timer {
         return mark();
     }
 };
-
-void pool_keep_memory(int dev) {
-    static bool done[64] = {false};
-    if (dev < 0 || dev >= 64 || done[dev]) return;
-    hipMemPool_t pool;
-    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-        uint64_t thr = UINT64_MAX;
-        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-    }
-    done[dev] = true;
-}
-
-int lds_limit(int dev) {
-    int v = 65536;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || v <= 0) {
-        v = 65536;
-        (void)hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-    }
-    return v;
-}
 
 // The total viewshed on the device: one chunk of sectors at a time, relocation -> sweep ->
 // back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
@@ -578,6 +569,26 @@ int tvs_los_evals(int32_t rows, int32_t cols, double spacing, int32_t n_sectors,
     for (int k = 0; k < n_sectors; ++k) count_sector(plan_sector(k, n_sectors, rows, cols, spacing, max_dist), ev, pr);
     *out_evals = ev;
     *out_pairs = pr;
+    return TVS_OK;
+}
+
+int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,
+                             void *hip_stream) {
+    g_err[0] = 0;
+    if (!tiles || ntiles < 1) return fail(TVS_EINVAL, "at least one tile");
+    if (int rc = check_flags(flags, true)) return rc;
+    if (flags & TVS_FLAG_COUNT_EVALS) return fail(TVS_EINVAL, "TVS_FLAG_COUNT_EVALS needs a stats argument");
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        if (!T.d_dem || !T.d_out) return fail(TVS_EINVAL, "tile %d: null d_dem or d_out", t);
+        if (int rc = check_scalars(T.rows, T.cols, T.spacing, T.obs_height, n_sectors, T.max_dist)) return rc;
+    }
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        if (int rc = run_total(T.d_dem, T.rows, T.cols, T.spacing, T.obs_height, n_sectors, T.max_dist, T.d_out,
+                               flags, nullptr, (hipStream_t)hip_stream, -1, nullptr, nullptr))
+            return rc;
+    }
     return TVS_OK;
 }
 

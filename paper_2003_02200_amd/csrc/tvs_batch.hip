@@ -1,0 +1,465 @@
+// tvs_batch.hip -- total viewsheds of many independent DEM tiles of uneven size as one batch.
+//
+// Each tile is its own total viewshed (Section 4.1 steps 1a-1d); the tiles share the sector
+// count. Per chunk of sectors, one persistent workgroup pool walks the list of every
+// (tile, sector, skewed row) item of every tile -- gathering each skewed row straight from its
+// tile's DEM (the relocation fused into the sweep) -- and one back-projection launch covers all
+// tiles. The whole pass is captured once into a HIP graph and replayed; the work lists live in
+// device memory and a replay only resets the item counters (with a fill kernel). The launch
+// shape of the persistent sweep (waves per workgroup, workgroups per CU) is picked by timing
+// candidates on a sample of the batch, and remembered per size class.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/libtvs.h"
+#include "tvs_geom.h"
+#include "tvs_host.h"
+#include "tvs_internal.h"
+
+using namespace tvs;
+using namespace tvs::host;
+
+namespace {
+
+struct ChunkPlan {
+    int k0, k1;       // sectors [k0, k1)
+    size_t ent_off;   // first BatchEnt of the chunk (tile t, sector k0 + x at ent_off + t * nsec + x)
+    size_t tile_off;  // first BatchTile of the chunk
+    size_t item_off;  // first work item of the chunk
+    int nitems;       // (tile, sector, skewed row) items
+    int nblocks;      // back-projection blocks over every tile
+    size_t vbytes;    // skewed viewshed rows of every tile and sector of the chunk
+};
+
+struct Shape {
+    int waves;   // wavefronts per workgroup of the persistent sweep
+    int per_cu;  // workgroups per CU
+};
+
+constexpr Shape kDefaultShape{4, 8};
+const Shape kCandidates[] = {{2, 4}, {2, 8}, {2, 16}, {4, 2}, {4, 4}, {4, 8}, {8, 1}, {8, 2}, {8, 4}};
+
+// Shapes chosen by timing, per (precision, slope form, size class of the longest row, of the
+// distance bound).
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, Shape> g_tuned;
+
+int ceil_log2(int64_t v) {
+    int r = 0;
+    while (((int64_t)1 << r) < v) ++r;
+    return r;
+}
+
+int cu_count(int dev) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    return v;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Skewed row index of the i-th row taken from a sector: middle-out, long rows first.
+int middle_out(int i, int nrows) {
+    const int c = (nrows - 1) >> 1;
+    return (i & 1) ? c + ((i + 1) >> 1) : c - (i >> 1);
+}
+
+}  // namespace
+
+struct tvs_batch {
+    int dev = 0;
+    int ntiles = 0, n = 0;
+    uint32_t flags = 0;
+    bool f64 = true, rcp = true, count = false;
+    std::vector<tvs_tile> tiles;
+    std::vector<std::vector<Sector>> sectors;  // per tile
+    std::vector<ChunkPlan> chunks;
+    int maxWx = 0, tabN = 0, maxK = 0;
+    bool counted = false;
+    int64_t evals = 0, pairs = 0;
+    size_t dbytes = 0;
+    char *dmem = nullptr;
+    float2 *tab32 = nullptr;
+    double2 *tab64 = nullptr;
+    unsigned int *counters = nullptr;
+    unsigned long long *work = nullptr;
+    BatchEnt *ent = nullptr;
+    BatchTile *btiles = nullptr;
+    uint32_t *items = nullptr;
+    uint32_t *V = nullptr;
+    Shape shape = kDefaultShape;
+    int grid = 0;
+    bool tuned = false;
+    double tune_ms = 0.0;
+    int launches = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~tvs_batch() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) {
+            (void)hipStreamSynchronize(cap);
+            (void)hipStreamDestroy(cap);
+        }
+        if (dmem) {
+            (void)hipDeviceSynchronize();
+            (void)hipFree(dmem);
+        }
+    }
+};
+
+namespace {
+
+int check_tiles(const tvs_tile *tiles, int ntiles, int n) {
+    if (!tiles || ntiles < 1) return fail(TVS_EINVAL, "a batch needs at least one tile");
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        if (!T.d_dem || !T.d_out) return fail(TVS_EINVAL, "tile %d: null d_dem or d_out", t);
+        if (int rc = check_scalars(T.rows, T.cols, T.spacing, T.obs_height, n, T.max_dist)) {
+            char msg[512];
+            snprintf(msg, sizeof(msg), "tile %d: %s", t, g_err);
+            return fail(rc, "%s", msg);
+        }
+    }
+    return TVS_OK;
+}
+
+int check_batch_flags(uint32_t flags) {
+    const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F32 | TVS_FLAG_COUNT_EVALS |
+                           TVS_FLAG_AUTOTUNE;
+    if (flags & ~known)
+        return fail(TVS_EINVAL, "unsupported flags 0x%x for a batch (the batched sweep always uses the early exit)",
+                    flags);
+    if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
+    return TVS_OK;
+}
+
+// Sector groups of the batch: every tile's sectors [k0, k1) together, within the scratch budget
+// and the item format (entries of a chunk < 2^16).
+int plan_chunks(tvs_batch *b, size_t budget) {
+    std::vector<int> pitch(b->ntiles);
+    for (int t = 0; t < b->ntiles; ++t) pitch[t] = pitch_of(b->tiles[t].rows, b->tiles[t].cols);
+    int k = 0;
+    while (k < b->n) {
+        ChunkPlan c{};
+        c.k0 = c.k1 = k;
+        while (c.k1 < b->n && (int64_t)b->ntiles * (c.k1 - c.k0 + 1) < 65536) {
+            size_t add = 0;
+            for (int t = 0; t < b->ntiles; ++t) add += (size_t)b->sectors[t][c.k1].nrows * pitch[t] * 4;
+            if (c.k1 > c.k0 && c.vbytes + add > budget) break;
+            c.vbytes += add;
+            ++c.k1;
+        }
+        if (c.k1 == c.k0) return fail(TVS_ENOMEM, "a batch of %d tiles is too large for one sector", b->ntiles);
+        b->chunks.push_back(c);
+        k = c.k1;
+    }
+    return TVS_OK;
+}
+
+// Device tables of every chunk: entries, back-projection tiles and work items.
+void build_tables(tvs_batch *b, std::vector<BatchEnt> &ent, std::vector<BatchTile> &bt,
+                  std::vector<uint32_t> &items) {
+    std::vector<int> order(b->ntiles);
+    for (int t = 0; t < b->ntiles; ++t) order[t] = t;
+    // largest tiles first: their long rows start early, short rows fill the tail
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return (int64_t)b->tiles[x].rows * b->tiles[x].cols > (int64_t)b->tiles[y].rows * b->tiles[y].cols;
+    });
+    for (ChunkPlan &c : b->chunks) {
+        const int nsec = c.k1 - c.k0;
+        c.ent_off = ent.size();
+        c.tile_off = bt.size();
+        c.item_off = items.size();
+        int64_t off = 0;
+        int blk = 0;
+        for (int t = 0; t < b->ntiles; ++t) {
+            const tvs_tile &T = b->tiles[t];
+            const int pitch = pitch_of(T.rows, T.cols);
+            for (int x = 0; x < nsec; ++x) {
+                const Sector &s = b->sectors[t][c.k0 + x];
+                BatchEnt e;
+                memset(&e, 0, sizeof(e));
+                e.s.T = s.T;
+                e.s.scale = s.scale;
+                e.s.clip = s.clip;
+                e.s.off = off;
+                e.s.kase = s.kase;
+                e.s.K = s.K;
+                e.s.t0 = s.t0;
+                e.s.nrows = s.nrows;
+                e.dem = T.d_dem;
+                e.H = T.rows;
+                e.W = T.cols;
+                e.pitch = pitch;
+                e.h0 = T.obs_height;
+                e.h0f = (float)T.obs_height;
+                ent.push_back(e);
+                off += (int64_t)s.nrows * pitch;
+            }
+            BatchTile q;
+            memset(&q, 0, sizeof(q));
+            q.out = T.d_out;
+            q.H = T.rows;
+            q.W = T.cols;
+            q.ent0 = t * nsec;
+            q.bx = (T.cols + BATCH_BLOCK - 1) / BATCH_BLOCK;
+            q.blk0 = blk;
+            blk += q.bx * ((T.rows + BATCH_BLOCK - 1) / BATCH_BLOCK);
+            bt.push_back(q);
+        }
+        c.nblocks = blk;
+        for (int t : order)
+            for (int x = 0; x < nsec; ++x) {
+                const int nr = b->sectors[t][c.k0 + x].nrows;
+                const uint32_t e = (uint32_t)(t * nsec + x);
+                for (int i = 0; i < nr; ++i) items.push_back((e << 16) | (uint32_t)middle_out(i, nr));
+            }
+        c.nitems = (int)(items.size() - c.item_off);
+    }
+}
+
+hipError_t enqueue_pass(tvs_batch *b, hipStream_t st) {
+    hipError_t e;
+    if ((e = launch_divtab(b->tab32, b->tab64, b->tabN, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(b->counters, (int64_t)b->chunks.size(), 0u, st)) != hipSuccess) return e;
+    b->launches = 2;
+    if (b->count) {
+        if ((e = launch_fill_u32((uint32_t *)b->work, 128, 0u, st)) != hipSuccess) return e;
+        ++b->launches;
+    }
+    for (size_t ci = 0; ci < b->chunks.size(); ++ci) {
+        const ChunkPlan &c = b->chunks[ci];
+        if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + c.item_off, c.nitems, b->counters + ci, b->V,
+                                    b->tab32, b->tab64, b->f64, b->rcp, b->shape.waves, b->grid, b->maxWx,
+                                    b->count ? b->work : nullptr, st)) != hipSuccess)
+            return e;
+        if ((e = launch_backproj_batch(b->btiles + c.tile_off, b->ntiles, c.nblocks, b->ent + c.ent_off,
+                                       c.k1 - c.k0, b->V, ci == 0, st)) != hipSuccess)
+            return e;
+        b->launches += 2;
+    }
+    return hipSuccess;
+}
+
+// Times every candidate shape on a strided sample of the first chunk's items (an eager pass
+// first builds the reciprocal tables) and keeps the fastest.
+int autotune(tvs_batch *b, int cus) {
+    const ChunkPlan &c = b->chunks[0];
+    const int stride = std::max(1, c.nitems / 16384);
+    std::vector<uint32_t> sample;
+    std::vector<uint32_t> all((size_t)c.nitems);
+    HIPCHK(hipMemcpy(all.data(), b->items + c.item_off, all.size() * 4, hipMemcpyDeviceToHost));
+    for (int i = 0; i < c.nitems; i += stride) sample.push_back(all[i]);
+    uint32_t *d_sample = nullptr;
+    unsigned int *d_ctr = nullptr;
+    HIPCHK(hipMalloc((void **)&d_sample, sample.size() * 4 + 256));
+    d_ctr = (unsigned int *)((char *)d_sample + align256(sample.size() * 4));
+    const auto t0 = std::chrono::steady_clock::now();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = TVS_OK;
+    float best = 1e30f;
+    Shape pick = kDefaultShape;
+    do {
+        if (hipMemcpy(d_sample, sample.data(), sample.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
+            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+            launch_divtab(b->tab32, b->tab64, b->tabN, b->cap) != hipSuccess) {
+            rc = fail(TVS_EDEVICE, "autotune set-up failed: %s", hipGetErrorString(hipGetLastError()));
+            break;
+        }
+        for (const Shape &s : kCandidates) {
+            const int grid = cus * s.per_cu;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && rc == TVS_OK; ++rep) {  // the first run warms the caches
+                if (launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
+                                       s.waves, 0, b->maxWx, nullptr, b->cap) != hipSuccess ||
+                    launch_fill_u32(d_ctr, 1, 0u, b->cap) != hipSuccess || hipEventRecord(e0, b->cap) != hipSuccess ||
+                    launch_sweep_batch(b->ent + c.ent_off, d_sample, (int)sample.size(), d_ctr, b->V, b->tab32,
+                                       b->tab64, b->f64, b->rcp, s.waves, grid, b->maxWx, nullptr,
+                                       b->cap) != hipSuccess ||
+                    hipEventRecord(e1, b->cap) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                    hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                    rc = fail(TVS_EDEVICE, "autotune run failed: %s", hipGetErrorString(hipGetLastError()));
+            }
+            if (rc != TVS_OK) break;
+            if (ms < best) {
+                best = ms;
+                pick = s;
+            }
+        }
+    } while (0);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(b->cap);
+    (void)hipFree(d_sample);
+    if (rc != TVS_OK) return rc;
+    b->shape = pick;
+    b->tuned = true;
+    b->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return TVS_OK;
+}
+
+int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *b) {
+    b->ntiles = ntiles;
+    b->n = n;
+    b->flags = flags;
+    b->f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
+    b->rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
+    b->count = (flags & TVS_FLAG_COUNT_EVALS) != 0;
+    b->tiles.assign(tiles, tiles + ntiles);
+    HIPCHK(hipGetDevice(&b->dev));
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        std::vector<Sector> S;
+        S.reserve(n);
+        for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist));
+        for (const Sector &s : S) b->maxK = std::max(b->maxK, std::min(s.K, std::max(s.Hx, s.Wx)));
+        b->sectors.push_back(std::move(S));
+        b->maxWx = std::max(b->maxWx, std::max(T.rows, T.cols));
+    }
+    b->tabN = b->maxWx;
+    if (sweep_lds_bytes(b->maxWx, b->f64) + 64 > (size_t)lds_limit(b->dev))
+        return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS", b->maxWx,
+                    b->f64 ? "double" : "float");
+    if (int rc = plan_chunks(b, scratch_budget())) return rc;
+    std::vector<BatchEnt> ent;
+    std::vector<BatchTile> bt;
+    std::vector<uint32_t> items;
+    build_tables(b, ent, bt, items);
+    size_t maxV = 0;
+    for (const ChunkPlan &c : b->chunks) maxV = std::max(maxV, c.vbytes);
+    const size_t nch = b->chunks.size();
+    const size_t sz_tab32 = align256((size_t)b->tabN * sizeof(float2));
+    const size_t sz_tab64 = align256((size_t)b->tabN * sizeof(double2));
+    const size_t sz_ctr = align256(nch * sizeof(unsigned int));
+    const size_t sz_work = align256(64 * sizeof(unsigned long long));
+    const size_t sz_ent = align256(ent.size() * sizeof(BatchEnt));
+    const size_t sz_bt = align256(bt.size() * sizeof(BatchTile));
+    const size_t sz_items = align256(items.size() * sizeof(uint32_t));
+    b->dbytes = sz_tab32 + sz_tab64 + sz_ctr + sz_work + sz_ent + sz_bt + sz_items + align256(maxV);
+    if (hipMalloc((void **)&b->dmem, b->dbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        b->dmem = nullptr;
+        return fail(TVS_ENOMEM, "batch device memory of %zu bytes not available", b->dbytes);
+    }
+    char *p = b->dmem;
+    b->tab32 = (float2 *)p; p += sz_tab32;
+    b->tab64 = (double2 *)p; p += sz_tab64;
+    b->counters = (unsigned int *)p; p += sz_ctr;
+    b->work = (unsigned long long *)p; p += sz_work;
+    b->ent = (BatchEnt *)p; p += sz_ent;
+    b->btiles = (BatchTile *)p; p += sz_bt;
+    b->items = (uint32_t *)p; p += sz_items;
+    b->V = (uint32_t *)p;
+    HIPCHK(hipMemcpy(b->ent, ent.data(), ent.size() * sizeof(BatchEnt), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->btiles, bt.data(), bt.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(b->items, items.data(), items.size() * sizeof(uint32_t), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(b->work, 0, 64 * sizeof(unsigned long long)));
+    HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+
+    const int cus = cu_count(b->dev);
+    const auto key = std::make_tuple((int)b->f64, (int)b->rcp, ceil_log2(b->maxWx), ceil_log2(b->maxK + 1));
+    if (flags & TVS_FLAG_AUTOTUNE) {
+        if (int rc = autotune(b, cus)) return rc;
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        g_tuned[key] = b->shape;
+    } else {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            b->shape = it->second;
+            b->tuned = true;
+        }
+    }
+    b->grid = cus * b->shape.per_cu;
+    // raise the sweep's LDS limit before capture (no attribute calls inside a graph)
+    HIPCHK(launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
+                              b->shape.waves, 0, b->maxWx, nullptr, b->cap));
+    HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    const hipError_t le = enqueue_pass(b, b->cap);
+    const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess) return fail(TVS_EDEVICE, "batch capture: %s", hipGetErrorString(le));
+    if (ce != hipSuccess) return fail(TVS_EDEVICE, "batch capture: %s", hipGetErrorString(ce));
+    HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return TVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvs_batch_create(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,
+                     tvs_batch **out_batch) {
+    g_err[0] = 0;
+    if (!out_batch) return fail(TVS_EINVAL, "null out_batch");
+    if (n_sectors < 1 || n_sectors > TVS_MAX_SECTORS)
+        return fail(TVS_EINVAL, "n_sectors must be in [1, %d]", TVS_MAX_SECTORS);
+    if (int rc = check_batch_flags(flags)) return rc;
+    if (int rc = check_tiles(tiles, ntiles, n_sectors)) return rc;
+    tvs_batch *b = new (std::nothrow) tvs_batch;
+    if (!b) return fail(TVS_ENOMEM, "host memory for the batch plan");
+    const int rc = create(tiles, ntiles, n_sectors, flags, b);
+    if (rc != TVS_OK) {
+        delete b;
+        return rc;
+    }
+    *out_batch = b;
+    return TVS_OK;
+}
+
+int tvs_batch_run(tvs_batch *batch, void *hip_stream) {
+    g_err[0] = 0;
+    if (!batch || !batch->exec) return fail(TVS_EINVAL, "null or unbuilt batch");
+    HIPCHK(hipGraphLaunch(batch->exec, (hipStream_t)hip_stream));
+    return TVS_OK;
+}
+
+int tvs_batch_get_info(const tvs_batch *batch, tvs_batch_info *info) {
+    g_err[0] = 0;
+    if (!batch || !info) return fail(TVS_EINVAL, "null batch or info");
+    tvs_batch *b = const_cast<tvs_batch *>(batch);
+    if (!b->counted) {
+        for (int t = 0; t < b->ntiles; ++t)
+            for (const Sector &s : b->sectors[t]) count_sector(s, b->evals, b->pairs);
+        b->counted = true;
+    }
+    memset(info, 0, sizeof(*info));
+    info->tiles = b->ntiles;
+    info->chunks = (int32_t)b->chunks.size();
+    info->kernel_launches = b->launches;
+    info->waves_per_group = b->shape.waves;
+    info->groups = b->grid;
+    info->tuned = b->tuned ? 1 : 0;
+    info->los_evals = b->evals;
+    info->pov_sector_pairs = b->pairs;
+    info->scratch_bytes = (int64_t)b->dbytes;
+    info->tune_ms = b->tune_ms;
+    if (b->count) {
+        unsigned long long h[64];
+        HIPCHK(hipDeviceSynchronize());
+        HIPCHK(hipMemcpy(h, b->work, sizeof(h), hipMemcpyDeviceToHost));
+        for (int x = 0; x < 64; ++x) info->sweep_evals_done += (int64_t)h[x];
+    }
+    return TVS_OK;
+}
+
+int tvs_batch_destroy(tvs_batch *batch) {
+    g_err[0] = 0;
+    delete batch;
+    return TVS_OK;
+}
+
+}  // extern "C"

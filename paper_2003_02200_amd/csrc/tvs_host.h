@@ -1,0 +1,59 @@
+// tvs_host.h -- host-side helpers shared by the C entry points of libtvs (not part of the C
+// ABI): error text, argument checks and the per-sector plan.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "tvs_geom.h"
+
+namespace tvs {
+namespace host {
+
+// Text of the last failure on the calling thread (tvs_last_error).
+extern thread_local char g_err[512];
+
+// Records the message and returns `code`.
+int fail(int code, const char *fmt, ...);
+
+#define HIPCHK(call)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail(TVS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// One sector of the plan (host side).
+struct Sector {
+    int kase, Hx, Wx;
+    double T;      // tan s'
+    double rho;    // max_dist cos s' / spacing
+    int K;         // last target index in range (TVS_K_UNBOUNDED when max_dist never binds)
+    double scale;  // (pi / 2n) spacing^2 / cos^2 s'
+    double clip;   // rho^2 - K^2
+    int t0, nrows;
+};
+
+// Elevations and the observer height must be finite, and either 0 or at least 2^-60 m in
+// magnitude. The second rule keeps every quantity of the sweep a multiple of 2^-83, so no slope
+// underflows to a signed zero (the kernels read strict comparisons from sign bits).
+constexpr double TVS_MIN_MAGNITUDE = 0x1p-60;
+
+Sector plan_sector(int k, int n, int H, int W, double dx, double R);
+bool magnitude_ok(double v);
+int check_scalars(int rows, int cols, double dx, double h0, int n, double R);
+int check_host_dem(const float *dem, int rows, int cols);
+int check_flags(uint32_t flags, bool accumulation);
+// Closed-form line-of-sight evaluations and POV-sector pairs of one sector.
+void count_sector(const Sector &s, int64_t &evals, int64_t &pairs);
+// Row pitch (elements) of a grid's skewed buffers.
+int pitch_of(int H, int W);
+// Device scratch a call may take: TVS_SCRATCH_MB, else min(free / 2, 16 GiB).
+size_t scratch_budget();
+// Keeps freed stream-ordered memory in the device's pool (no release between calls).
+void pool_keep_memory(int dev);
+// Largest LDS a workgroup of this device may request.
+int lds_limit(int dev);
+
+}  // namespace host
+}  // namespace tvs

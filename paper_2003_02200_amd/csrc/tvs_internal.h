@@ -39,6 +39,27 @@ struct ChunkArgs {
     int32_t pad0, pad1;
 };
 
+// One (tile, sector) of a batch chunk: the sector's geometry (off = element offset of its skewed
+// viewshed rows in the chunk buffer) and the tile it belongs to.
+struct BatchEnt {
+    SecDev s;
+    const float *dem;  // the tile's DEM (device)
+    int32_t H, W;      // tile dims
+    int32_t pitch;     // row pitch of this tile's skewed rows
+    float h0f;         // observer height rounded to float
+    double h0;         // observer height
+};
+
+// A tile of a batch, as the batched back-projection sees it.
+struct BatchTile {
+    double *out;       // the tile's total-viewshed map (device)
+    int32_t H, W;
+    int32_t ent0;      // first BatchEnt of this tile in the chunk (its sectors follow)
+    int32_t bx;        // 64 x 64 cell blocks per block row
+    int32_t blk0;      // first flat block of this tile
+    int32_t pad;
+};
+
 // Launchers (tvs_kernels.hip). All enqueue on `st` and return the launch status.
 hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st);
 hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw,
@@ -53,6 +74,15 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
 hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first,
                                hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+// Batched path: a persistent fused relocate + sweep over a chunk's (tile, sector, row) items,
+// then one back-projection launch over every tile of the chunk. launch_sweep_batch with
+// grid == 0 only prepares the kernel's LDS limit.
+hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
+                              uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
+                              int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st);
+hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
+                                 const uint32_t *V, int first, hipStream_t st);
 size_t sweep_lds_bytes(int maxWx, bool f64);
+constexpr int BATCH_BLOCK = 64;  // cells per side of a back-projection block
 
 }  // namespace tvs

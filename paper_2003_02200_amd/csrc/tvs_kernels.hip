@@ -460,32 +460,21 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
     return nt;
 }
 
+// Sweeps a skewed row of nt samples held in LDS (row[TVS_SWEEP_PAD + q], -inf sentinels on both
+// sides, room for the early exit's block maxima after them) and stores U | e << 30 of POV q at
+// dst[q]. Returns the evaluations this lane carried out when `count` is set.
 template <typename Tz, int NW, bool RCP, bool PRUNE>
-__global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
-                                                   uint32_t *__restrict__ V,
-                                                   const typename Tab<Tz>::type *__restrict__ tab,
-                                                   unsigned long long *__restrict__ work) {
-    extern __shared__ __align__(16) unsigned char lds_raw[];
-    Tz *row = reinterpret_cast<Tz *>(lds_raw);
-    __shared__ unsigned long long wg_work;
-    const SecDev &s = a.s[blockIdx.y];
-    if ((int)blockIdx.x >= s.nrows) return;
-    const int ri = row_of_block(blockIdx.x, s.nrows);
-    int jlo;
-    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
-    if (nt == 0) return;
+__device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
+                                              const typename Tab<Tz>::type *__restrict__ tab,
+                                              uint32_t *__restrict__ dst, bool count) {
     const int nb = (nt + 31) >> 5;
     Tz *suf = row + nt + 2 * TVS_SWEEP_PAD;
     Tz *pre = suf + nb;
     if (PRUNE) block_bounds(row + TVS_SWEEP_PAD, nb, suf, pre);
-    if (work && threadIdx.x == 0) wg_work = 0;
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int K = s.K;
-    const Tz h0 = h0_of<Tz>(a);
     const int nseg = (nt + 63) >> 6;
-    uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
-    uint32_t evals = 0;  // line-of-sight evaluations this lane carried out (with work counting)
+    uint32_t evals = 0;
     for (int sg = wv; sg < nseg; sg += NW) {
         const int q0 = sg << 6;
         const int q = q0 + lane;
@@ -501,16 +490,116 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
         e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, q0, live, df);
         e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, top, live, db);
         if (live) dst[q] = U | (e << 30);
-        if (work && live) evals += (uint32_t)(min(df, min(K, nt - 1 - q)) + min(db, min(K, q)));
+        if (count && live) evals += (uint32_t)(min(df, min(K, nt - 1 - q)) + min(db, min(K, q)));
     }
-    if (work) {
-        // one atomic per workgroup, spread over 64 counters
-        const uint32_t wsum = wave_sum_u32(evals);
-        __syncthreads();
-        if (lane == 0) atomicAdd(&wg_work, (unsigned long long)wsum);
-        __syncthreads();
-        if (threadIdx.x == 0) atomicAdd(&work[(blockIdx.x + 7 * blockIdx.y) & 63], wg_work);
+    return evals;
+}
+
+// Adds a workgroup's evaluation count to one of 64 counters: one atomic per workgroup.
+__device__ __forceinline__ void add_work(unsigned long long *work, unsigned long long &wg_work,
+                                         unsigned long long evals, int slot) {
+    for (int o = 32; o > 0; o >>= 1) evals += __shfl_xor(evals, o, 64);
+    const unsigned long long wsum = evals;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) atomicAdd(&wg_work, wsum);
+    __syncthreads();
+    if (threadIdx.x == 0) atomicAdd(&work[slot & 63], wg_work);
+}
+
+template <typename Tz, int NW, bool RCP, bool PRUNE>
+__global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
+                                                   uint32_t *__restrict__ V,
+                                                   const typename Tab<Tz>::type *__restrict__ tab,
+                                                   unsigned long long *__restrict__ work) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Tz *row = reinterpret_cast<Tz *>(lds_raw);
+    __shared__ unsigned long long wg_work;
+    const SecDev &s = a.s[blockIdx.y];
+    if ((int)blockIdx.x >= s.nrows) return;
+    const int ri = row_of_block(blockIdx.x, s.nrows);
+    int jlo;
+    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
+    if (nt == 0) return;
+    if (work && threadIdx.x == 0) wg_work = 0;
+    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE>(row, nt, s.K, h0_of<Tz>(a), tab,
+                                                         V + s.off + (int64_t)ri * a.pitch + jlo, work != nullptr);
+    if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
+}
+
+// ------------------------------------------------------------------- batched, fused sweep
+// Skewed row ri of a sector gathered straight from the DEM into LDS, with the relocation's
+// interpolation (the same FP64 blend, rows clamped, -0 made +0), so the batched path needs no
+// skwDEM buffer in HBM. Reads along a skewed row touch one grid row (cases 0/3) or one grid
+// column (cases 1/2) per sample; neighbouring skewed rows reuse the same cache lines.
+template <typename Tz>
+__device__ __forceinline__ int gather_row(const float *__restrict__ dem, int H, int W, const SecDev &s, int ri,
+                                          Tz *row, int &jlo) {
+    int Hx, Wx;
+    frame_dims(s.kase, H, W, Hx, Wx);
+    const int t = s.t0 + ri;
+    jlo = row_first(s.T, t, Hx, Wx);
+    const int jhi = row_last(s.T, t, Hx, Wx);
+    const int nt = jhi - jlo + 1;
+    if (nt <= 0) return 0;
+    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
+        const int q = x - TVS_SWEEP_PAD;
+        Tz v = neg_inf<Tz>();
+        if (q >= 0 && q < nt) {
+            const int j = jlo + q;
+            int d;
+            double r;
+            col_offset(s.T, j, d, r);
+            const int u = t + d;
+            const float av = dem[frame_index(s.kase, W, min(max(u, 0), Hx - 1), j)];
+            double z = (double)av;
+            if (r != 0.0 && u >= 0 && u < Hx - 1) {
+                const float bv = dem[frame_index(s.kase, W, u + 1, j)];
+                z = __dadd_rn(__dmul_rn(__dsub_rn(1.0, r), (double)av), __dmul_rn(r, (double)bv));
+            }
+            v = add_rn((Tz)z, (Tz)0);
+        }
+        row[x] = v;
     }
+    __syncthreads();
+    return nt;
+}
+
+template <typename Tz> __device__ __forceinline__ Tz h0_of(const BatchEnt &e);
+template <> __device__ __forceinline__ float h0_of<float>(const BatchEnt &e) { return e.h0f; }
+template <> __device__ __forceinline__ double h0_of<double>(const BatchEnt &e) { return e.h0; }
+
+// Persistent sweep over every (tile, sector, skewed row) item of a batch chunk: each workgroup
+// takes the next item from a device counter until the list is exhausted (every workgroup
+// reaches the end, the counter only grows), gathers the row from its tile's DEM and sweeps it.
+template <typename Tz, int NW, bool RCP>
+__global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restrict__ ent,
+                                                         const uint32_t *__restrict__ items, int nitems,
+                                                         unsigned int *__restrict__ counter, uint32_t *__restrict__ V,
+                                                         const typename Tab<Tz>::type *__restrict__ tab,
+                                                         unsigned long long *__restrict__ work) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Tz *row = reinterpret_cast<Tz *>(lds_raw);
+    __shared__ int next;
+    __shared__ unsigned long long wg_work;
+    if (work && threadIdx.x == 0) wg_work = 0;
+    unsigned long long evals = 0;
+    for (;;) {
+        if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int it = __builtin_amdgcn_readfirstlane(next);
+        __syncthreads();  // every thread has read `next` before thread 0 writes it again
+        if (it >= nitems) break;
+        const uint32_t item = items[it];
+        const BatchEnt &E = ent[item >> 16];
+        const int ri = (int)(item & 0xffffu);
+        int jlo;
+        const int nt = gather_row<Tz>(E.dem, E.H, E.W, E.s, ri, row, jlo);
+        if (nt > 0)
+            evals += sweep_row<Tz, NW, RCP, true>(row, nt, E.s.K, h0_of<Tz>(E), tab,
+                                                  V + E.s.off + (int64_t)ri * E.pitch + jlo, work != nullptr);
+        __syncthreads();  // the row is read by every wavefront before the next gather
+    }
+    if (work) add_work(work, wg_work, evals, blockIdx.x);
 }
 
 // Comparison variant: one wavefront per POV and direction, lanes = 64 consecutive targets,
@@ -584,24 +673,26 @@ constexpr int BP_LP = BP_T + 1;
 constexpr int BP_MAXR = 2 * BP_T + 3;
 constexpr int BP_CELLS = BP_T * BP_T / 256;
 
-template <bool KAHAN>
-__global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint32_t *__restrict__ V,
-                                                  double *__restrict__ out, float *__restrict__ ksum,
-                                                  float *__restrict__ kc, int first, int last) {
+// The 64 x 64 cell block at (i0, j0) of an H x W grid over sectors sec(0) .. sec(nsec - 1),
+// whose skewed viewshed rows have the given pitch.
+template <bool KAHAN, typename SecFn>
+__device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W, int pitch,
+                                               const uint32_t *__restrict__ V, double *__restrict__ out,
+                                               float *__restrict__ ksum, float *__restrict__ kc, int first,
+                                               int last, int i0, int j0) {
     __shared__ uint32_t tile[BP_MAXR * BP_LP];
     __shared__ int col_d[BP_T];
     __shared__ double col_r[BP_T];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int i0 = blockIdx.y * BP_T, j0 = blockIdx.x * BP_T;
     const int j = j0 + lane;
     double acc[BP_CELLS];
     float fs[BP_CELLS], fc[BP_CELLS];
 #pragma unroll
     for (int c = 0; c < BP_CELLS; ++c) {
         const int i = i0 + wv + 4 * c;
-        const bool in = i < a.H && j < a.W;
-        const int64_t cell = (int64_t)i * a.W + j;
+        const bool in = i < H && j < W;
+        const int64_t cell = (int64_t)i * W + j;
         if (KAHAN) {
             fs[c] = (first || !in) ? 0.0f : ksum[cell];
             fc[c] = (first || !in) ? 0.0f : kc[cell];
@@ -609,16 +700,16 @@ __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint3
             acc[c] = (first || !in) ? 0.0 : out[cell];
         }
     }
-    const int ilast = min(i0 + BP_T, a.H) - 1, jlast = min(j0 + BP_T, a.W) - 1;
-    for (int k = 0; k < a.nsec; ++k) {
-        const SecDev &s = a.s[k];
+    const int ilast = min(i0 + BP_T, H) - 1, jlast = min(j0 + BP_T, W) - 1;
+    for (int k = 0; k < nsec; ++k) {
+        const SecDev &s = sec(k);
         // the block's base-frame rectangle [plo, phi] x [qlo, qhi]
         int plo, phi, qlo, qhi;
         switch (s.kase) {
         case 0: plo = i0; phi = ilast; qlo = j0; qhi = jlast; break;
         case 1: plo = j0; phi = jlast; qlo = i0; qhi = ilast; break;
-        case 2: plo = a.W - 1 - jlast; phi = a.W - 1 - j0; qlo = i0; qhi = ilast; break;
-        default: plo = i0; phi = ilast; qlo = a.W - 1 - jlast; qhi = a.W - 1 - j0; break;
+        case 2: plo = W - 1 - jlast; phi = W - 1 - j0; qlo = i0; qhi = ilast; break;
+        default: plo = i0; phi = ilast; qlo = W - 1 - jlast; qhi = W - 1 - j0; break;
         }
         int dlo, dhi;
         double rtmp;
@@ -636,17 +727,17 @@ __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint3
             col_r[threadIdx.x] = r;
         }
         if (lane < nq) {
-            const uint32_t *src = V + s.off + (int64_t)rbase * a.pitch + qlo + lane;
-            for (int rr = wv; rr < nr; rr += 4) tile[rr * BP_LP + lane] = src[(int64_t)rr * a.pitch];
+            const uint32_t *src = V + s.off + (int64_t)rbase * pitch + qlo + lane;
+            for (int rr = wv; rr < nr; rr += 4) tile[rr * BP_LP + lane] = src[(int64_t)rr * pitch];
         }
         __syncthreads();
         const float scf = (float)s.scale;
 #pragma unroll
         for (int c = 0; c < BP_CELLS; ++c) {
             const int i = i0 + wv + 4 * c;
-            if (i >= a.H || j >= a.W) continue;
+            if (i >= H || j >= W) continue;
             int p, q;
-            to_frame(s.kase, a.W, i, j, p, q);
+            to_frame(s.kase, W, i, j, p, q);
             const int cq = q - qlo;
             const int d = col_d[cq];
             const double r = col_r[cq];
@@ -677,8 +768,8 @@ __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint3
 #pragma unroll
     for (int c = 0; c < BP_CELLS; ++c) {
         const int i = i0 + wv + 4 * c;
-        if (i >= a.H || j >= a.W) continue;
-        const int64_t cell = (int64_t)i * a.W + j;
+        if (i >= H || j >= W) continue;
+        const int64_t cell = (int64_t)i * W + j;
         if (KAHAN) {
             if (last) out[cell] = (double)fs[c] - (double)fc[c];
             else { ksum[cell] = fs[c]; kc[cell] = fc[c]; }
@@ -686,6 +777,31 @@ __global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint3
             out[cell] = acc[c];
         }
     }
+}
+
+template <bool KAHAN>
+__global__ __launch_bounds__(256) void k_backproj(const ChunkArgs a, const uint32_t *__restrict__ V,
+                                                  double *__restrict__ out, float *__restrict__ ksum,
+                                                  float *__restrict__ kc, int first, int last) {
+    backproj_block<KAHAN>([&](int k) -> const SecDev & { return a.s[k]; }, a.nsec, a.H, a.W, a.pitch, V, out, ksum,
+                          kc, first, last, blockIdx.y * BP_T, blockIdx.x * BP_T);
+}
+
+// Every tile of a batch chunk: flat block b belongs to the last tile whose first block is <= b.
+__global__ __launch_bounds__(256) void k_backproj_batch(const BatchTile *__restrict__ tiles, int ntiles,
+                                                        const BatchEnt *__restrict__ ent, int nsec,
+                                                        const uint32_t *__restrict__ V, int first) {
+    int lo = 0, hi = ntiles - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tiles[mid].blk0 <= (int)blockIdx.x) lo = mid;
+        else hi = mid - 1;
+    }
+    const BatchTile &T = tiles[lo];
+    const int b = (int)blockIdx.x - T.blk0;
+    const BatchEnt *e = ent + T.ent0;
+    backproj_block<false>([&](int k) -> const SecDev & { return e[k].s; }, nsec, T.H, T.W, e[0].pitch, V, T.out,
+                          nullptr, nullptr, first, 1, (b / T.bx) * BP_T, (b % T.bx) * BP_T);
 }
 
 // ------------------------------------------------------------------------------ singular
@@ -856,6 +972,42 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
     else if (f64) k_singular<double, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
     else if (rcp) k_singular<float, true><<<blocks, 256, 0, st>>>(a, dem, rayV);
     else k_singular<float, false><<<blocks, 256, 0, st>>>(a, dem, rayV);
+    return hipGetLastError();
+}
+
+// With grid == 0 only the kernel's LDS limit is raised (outside any graph capture).
+hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
+                              uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
+                              int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st) {
+    const size_t lds = sweep_lds_bytes(maxWx, f64);
+    hipError_t e = hipSuccess;
+#define TVS_BATCH_GO(TZ, NW, RCP, TAB)                                                                  \
+    do {                                                                                                \
+        auto f = k_sweep_batch<TZ, NW, RCP>;                                                            \
+        if (grid == 0) return set_lds(f, lds);                                                          \
+        f<<<grid, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work);                       \
+    } while (0)
+    switch (waves) {
+    case 2:
+        if (f64) { if (rcp) TVS_BATCH_GO(double, 2, true, tab64); else TVS_BATCH_GO(double, 2, false, tab64); }
+        else { if (rcp) TVS_BATCH_GO(float, 2, true, tab32); else TVS_BATCH_GO(float, 2, false, tab32); }
+        break;
+    case 8:
+        if (f64) { if (rcp) TVS_BATCH_GO(double, 8, true, tab64); else TVS_BATCH_GO(double, 8, false, tab64); }
+        else { if (rcp) TVS_BATCH_GO(float, 8, true, tab32); else TVS_BATCH_GO(float, 8, false, tab32); }
+        break;
+    default:
+        if (f64) { if (rcp) TVS_BATCH_GO(double, 4, true, tab64); else TVS_BATCH_GO(double, 4, false, tab64); }
+        else { if (rcp) TVS_BATCH_GO(float, 4, true, tab32); else TVS_BATCH_GO(float, 4, false, tab32); }
+        break;
+    }
+#undef TVS_BATCH_GO
+    return hipGetLastError();
+}
+
+hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
+                                 const uint32_t *V, int first, hipStream_t st) {
+    k_backproj_batch<<<nblocks, 256, 0, st>>>(tiles, ntiles, ent, nsec, V, first);
     return hipGetLastError();
 }
 

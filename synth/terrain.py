@@ -31,6 +31,8 @@ __all__ = [
     "cone",
     "workload_dem",
     "WORKLOADS",
+    "batch_workload",
+    "BATCH64",
 ]
 
 
@@ -169,3 +171,24 @@ def workload_dem(name: str) -> np.ndarray:
     if "ridge_seed" in w:
         return ridged_dem(w["side"], w["seed"], w["roughness"], w["spacing"], w["ridge_seed"], w["zmax"])
     return fractal_dem(w["side"], w["seed"], w["roughness"], w["zmax"])
+
+
+# A batch of independent tiles of uneven size: square fractal tiles (roughness 0.55, 0-2500 m)
+# with sides drawn uniformly from [side_lo, side_hi], 10 m spacing, observer heights uniform in
+# [1.5, 30] m, max distance = tile extent; tile i uses terrain seed 4000 + i.
+BATCH64 = dict(ntiles=64, seed=4, side_lo=256, side_hi=2048, roughness=0.55, zmax=2500.0, spacing=10.0,
+               h_lo=1.5, h_hi=30.0, n_sectors=180)
+
+
+def batch_workload(ntiles: int = 64, seed: int = 4, side_lo: int = 256, side_hi: int = 2048) -> list:
+    """List of dicts (dem, spacing, obs_height, max_dist) for a batch of tiles."""
+    w = BATCH64
+    rng = np.random.default_rng(seed)
+    sides = rng.integers(side_lo, side_hi + 1, ntiles)
+    heights = rng.uniform(w["h_lo"], w["h_hi"], ntiles)
+    out = []
+    for i in range(ntiles):
+        side = int(sides[i])
+        out.append(dict(dem=fractal_dem(side, 4000 + i, w["roughness"], w["zmax"]), spacing=w["spacing"],
+                        obs_height=float(heights[i]), max_dist=side * w["spacing"]))
+    return out

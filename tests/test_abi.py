@@ -111,3 +111,25 @@ def test_plan_matches_oracle(tvs, orc, H, W, n, R):
         assert tvs.los_evals(H, W, 10.0, n, R) == orc.los_evals(H, W, 10.0, n, R)
     if (H, W) == (2000, 2000):
         assert tvs.los_evals(H, W, 10.0, n, R) == (920007832528, 720351824)
+
+
+def test_batch_rejects_bad_arguments(tvs):
+    """Batch validation happens before any device work: null lists, bad tiles, bad flags."""
+    L = tvs.lib()
+    h = C.c_void_p()
+    assert L.tvs_batch_create(None, 1, 8, 0, C.byref(h)) == -1
+    t = (tvs.Tile * 2)()
+    t[0] = tvs.Tile(16, 32, 4, 4, 10.0, 1.5, 100.0)  # never dereferenced: validation fails first
+    t[1] = tvs.Tile(16, 32, 4, 0, 10.0, 1.5, 100.0)  # zero columns
+    assert L.tvs_batch_create(t, 2, 8, 0, C.byref(h)) == -1
+    assert b"tile 1" in L.tvs_last_error()
+    t[1] = tvs.Tile(None, 32, 4, 4, 10.0, 1.5, 100.0)
+    assert L.tvs_batch_create(t, 2, 8, 0, C.byref(h)) == -1
+    t[1] = tvs.Tile(16, 32, 4, 4, 10.0, 1.5, 100.0)
+    for flags in (tvs.FLAG_SWEEP_SCAN, tvs.FLAG_ACC_KAHAN32, tvs.FLAG_NO_PRUNE, 0x41, 0x100):
+        assert L.tvs_batch_create(t, 2, 8, flags, C.byref(h)) == -1, flags
+    assert L.tvs_batch_create(t, 2, 0, 0, C.byref(h)) == -1
+    assert L.tvs_batch_create(t, 0, 8, 0, C.byref(h)) == -1
+    assert L.tvs_batch_run(None, None) == -1
+    assert L.tvs_batch_destroy(None) == 0
+    assert L.tvs_total_viewshed_tiles(None, 1, 8, 0, None) == -1

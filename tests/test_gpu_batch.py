@@ -1,0 +1,141 @@
+"""Batches of independent tiles (tvs_batch_*): the persistent fused relocate + sweep and the
+batched back-projection, replayed from a captured graph, against the plain per-tile path and
+the oracle (marked `gpu`)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from synth import fractal_dem
+
+pytestmark = pytest.mark.gpu
+P_DEFAULT, P_F32 = 65, 33
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tvs():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2003_02200_amd as t
+
+    t.lib()
+    return t
+
+
+# (rows, cols, spacing, obs_height, max_dist): uneven sizes, a 1-cell tile, a long strip, an
+# unbounded distance and a distance shorter than one cell
+TILES = [(40, 53, 10.0, 1.5, 530.0), (1, 1, 5.0, 2.0, 100.0), (97, 12, 10.0, 20.0, math.inf),
+         (64, 64, 7.5, 1.5, 480.0), (23, 140, 10.0, 3.0, 1400.0), (130, 77, 10.0, 30.0, 1300.0),
+         (16, 16, 10.0, 1.5, 4.0)]
+
+
+def _make(tiles, seed=0):
+    import torch
+
+    dems, host = [], []
+    for x, (H, W, dx, h0, R) in enumerate(tiles):
+        d = fractal_dem(max(H, W), 100 + seed + x, 0.6, 900.0)[:H, :W].copy()
+        host.append(d)
+        dems.append(torch.from_numpy(d).cuda())
+    return host, dems
+
+
+def _outs(tiles, fill):
+    import torch
+
+    return [torch.full((H, W), fill, dtype=torch.float64, device="cuda") for (H, W, *_r) in tiles]
+
+
+@pytest.mark.parametrize("flags,prec", [(0, P_DEFAULT), (0x40, P_F32)])
+def test_batch_equals_per_tile_and_oracle(tvs, orc, flags, prec):
+    import torch
+
+    n = 24
+    host, dems = _make(TILES)
+    outs_b = _outs(TILES, 7.0)  # stale values: the first chunk must overwrite them
+    outs_t = _outs(TILES, -1.0)
+    tl_b = [(dems[x], outs_b[x], *TILES[x][2:]) for x in range(len(TILES))]
+    tl_t = [(dems[x], outs_t[x], *TILES[x][2:]) for x in range(len(TILES))]
+    note(f"batch create flags={flags}")
+    b = tvs.Batch(tl_b, n, flags=flags)
+    tvs.total_viewshed_tiles(tl_t, n, flags=flags)
+    torch.cuda.synchronize()
+    want = [o.cpu().numpy() for o in outs_t]
+    for x, (H, W, dx, h0, R) in enumerate(TILES):
+        np.testing.assert_allclose(want[x], orc.total(host[x], dx, h0, n, R, prec=prec), rtol=1e-12, atol=0)
+    # replays of the captured pass, with eager work and synchronisation between them
+    for rep in range(3):
+        note(f"batch replay {rep} flags={flags}")
+        b.run()
+        torch.cuda.synchronize()
+        for x in range(len(TILES)):
+            np.testing.assert_allclose(outs_b[x].cpu().numpy(), want[x], rtol=1e-13, atol=0, err_msg=f"tile {x}")
+        for o in outs_b:
+            o.fill_(3.0)
+        torch.cuda.synchronize()
+    inf = b.info()
+    assert inf.tiles == len(TILES) and inf.chunks >= 1 and inf.kernel_launches == 2 + 2 * inf.chunks
+    ev = sum(tvs.los_evals(H, W, dx, n, R)[0] for (H, W, dx, h0, R) in TILES)
+    assert inf.los_evals == ev
+    b.close()
+
+
+def test_batch_counts_and_chunking(tvs, monkeypatch):
+    """A scratch budget small enough to force several chunks; evaluation counts equal the sum of
+    the single-tile counts (the same early exit row by row)."""
+    import torch
+
+    monkeypatch.setenv("TVS_SCRATCH_MB", "1")
+    n = 30
+    host, dems = _make(TILES, seed=5)
+    outs = _outs(TILES, 0.0)
+    tl = [(dems[x], outs[x], *TILES[x][2:]) for x in range(len(TILES))]
+    note("batch with forced chunking and counting")
+    b = tvs.Batch(tl, n, flags=tvs.FLAG_COUNT_EVALS)
+    b.run()
+    torch.cuda.synchronize()
+    inf = b.info()
+    assert inf.chunks > 1
+    done = 0
+    for x, (H, W, dx, h0, R) in enumerate(TILES):
+        ref, st = tvs.total_viewshed(dems[x], dx, h0, n, R, flags=tvs.FLAG_COUNT_EVALS, stats=True)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(outs[x].cpu().numpy(), ref.cpu().numpy(), rtol=1e-13, atol=0)
+        done += st.sweep_evals_done
+    assert inf.sweep_evals_done == done
+    b.run()  # a second pass counts again from zero
+    torch.cuda.synchronize()
+    assert b.info().sweep_evals_done == done
+    b.close()
+
+
+def test_batch_autotune(tvs):
+    import torch
+
+    n = 12
+    host, dems = _make(TILES[:4], seed=9)
+    outs = _outs(TILES[:4], 0.0)
+    tl = [(dems[x], outs[x], *TILES[x][2:]) for x in range(4)]
+    note("batch autotune")
+    b = tvs.Batch(tl, n, flags=tvs.FLAG_AUTOTUNE)
+    inf = b.info()
+    assert inf.tuned == 1 and inf.tune_ms > 0 and inf.waves_per_group in (2, 4, 8)
+    b.run()
+    torch.cuda.synchronize()
+    for x in range(4):
+        H, W, dx, h0, R = TILES[x]
+        ref = tvs.total_viewshed(dems[x], dx, h0, n, R)
+        torch.cuda.synchronize()
+        np.testing.assert_allclose(outs[x].cpu().numpy(), ref.cpu().numpy(), rtol=1e-13, atol=0)
+    # the shape is remembered for the size class
+    b2 = tvs.Batch(tl, n)
+    assert b2.info().tuned == 1 and b2.info().waves_per_group == inf.waves_per_group
+    b.close()
+    b2.close()
