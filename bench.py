@@ -75,9 +75,12 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=128, help="side of the centre window the oracle times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-summary", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.md"))
-    ap.add_argument("--mode", choices=("single", "batch"), default="single",
+    ap.add_argument("--mode", choices=("single", "batch", "serve"), default="single",
                     help="single: the 2000x2000 workload (the headline); batch: 64 independent tiles of uneven "
-                         "size through the batched path, against the plain per-tile loop")
+                         "size through the batched path, against the plain per-tile loop; serve: a Poisson stream "
+                         "of singular and total requests through the request server")
+    ap.add_argument("--serve-seconds", type=float, default=10.0)
+    ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-tiles", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="before timing, copy this many MiB device-to-device (a plain copy kernel of known size "
@@ -98,6 +101,8 @@ def main():
 
     if args.mode == "batch":
         return bench_batch(args)
+    if args.mode == "serve":
+        return bench_serve(args)
 
     w = WORKLOADS[args.workload]
     dem = workload_dem(args.workload)
@@ -304,6 +309,116 @@ def bench_batch(args):
         "max_rel_diff_vs_per_tile_loop": worst,
     }
     batch.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_serve(args):
+    """Request serving: resident fractal grids (singular pool 512..4096, total pool 256..1024,
+    10 m), a Poisson stream (seed 5) of 80 % singular requests (random POV, max distance = grid
+    extent) and 20 % total requests (max distance = grid extent), observer 1.5 m, 180 sectors.
+    Reports latency percentiles under the stream, then the capacity with every request queued at
+    once against the plain path that runs the same requests one by one."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    import paper_2003_02200_amd as tvs
+    from synth import fractal_dem
+
+    torch.cuda.set_device(0)
+    n, h0, dx = 180, 1.5, 10.0
+    sing_sides = [512, 1024, 1536, 2048, 3072, 4096]
+    tot_sides = [256, 384, 512, 640, 768, 1024]
+    t0 = time.perf_counter()
+    grids = [fractal_dem(sd, 500 + x, 0.55, 2500.0) for x, sd in enumerate(sing_sides + tot_sides)]
+    log(f"generated {len(grids)} grids in {time.perf_counter() - t0:.1f} s")
+    rng = np.random.default_rng(5)
+    reqs = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / args.serve_rate)
+        if t >= args.serve_seconds:
+            break
+        if rng.uniform() < 0.8:
+            g = int(rng.integers(0, len(sing_sides)))
+            sd = sing_sides[g]
+            reqs.append((t, "s", g, int(rng.integers(0, sd)), int(rng.integers(0, sd))))
+        else:
+            g = len(sing_sides) + int(rng.integers(0, len(tot_sides)))
+            reqs.append((t, "t", g, 0, 0))
+    R = [grids[r[2]].shape[0] * dx for r in reqs]
+    ev_total = sum(tvs.los_evals(grids[r[2]].shape[0], grids[r[2]].shape[1], dx, n, R[x])[0]
+                   for x, r in enumerate(reqs) if r[1] == "t")
+    log(f"{len(reqs)} requests over {args.serve_seconds} s ({sum(r[1] == 't' for r in reqs)} total)")
+
+    def run_server(paced):
+        srv = tvs.Server(streams=4, max_singular_batch=64)
+        ids = [srv.add_grid(g, dx) for g in grids]
+        tickets = [None] * len(reqs)
+        # warm the kernels
+        srv.wait(srv.submit_singular(ids[0], h0, n, R[0], 0, 0))
+        srv.wait(srv.submit_total(ids[-1], h0, n, grids[-1].shape[0] * dx))
+        torch.cuda.synchronize()
+        start = time.perf_counter()
+        for x, (ta, kind, g, i, j) in enumerate(reqs):
+            if paced:
+                delay = start + ta - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            tickets[x] = (srv.submit_singular(ids[g], h0, n, R[x], i, j) if kind == "s"
+                          else srv.submit_total(ids[g], h0, n, R[x]))
+        res = [srv.wait(tk) for tk in tickets]
+        wall = time.perf_counter() - start
+        st = srv.stats().as_dict()
+        for tk in tickets:
+            srv.release(tk)
+        srv.close()
+        return res, wall, st
+
+    log("paced stream ...")
+    res, wall, st = run_server(True)
+    lat = np.array([r.latency_ms for r in res])
+    lat_s = np.array([r.latency_ms for r, q in zip(res, reqs) if q[1] == "s"])
+    lat_t = np.array([r.latency_ms for r, q in zip(res, reqs) if q[1] == "t"])
+    assert all(r.status == 0 for r in res)
+    log(f"paced: p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms over {wall:.1f} s")
+    log("flood (every request queued at once) ...")
+    res_f, wall_f, st_f = run_server(False)
+    log(f"flood: {len(reqs) / wall_f:.1f} req/s")
+    log("plain path, one request at a time ...")
+    dg = [torch.from_numpy(g).cuda() for g in grids]
+    tvs.singular_viewshed(dg[0], dx, h0, n, R[0], 0, 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for x, (ta, kind, g, i, j) in enumerate(reqs):
+        if kind == "s":
+            tvs.singular_viewshed(dg[g], dx, h0, n, R[x], i, j)
+        else:
+            tvs.total_viewshed(dg[g], dx, h0, n, R[x])
+            torch.cuda.synchronize()
+    plain = time.perf_counter() - t1
+    log(f"plain: {len(reqs) / plain:.1f} req/s")
+    line = {
+        "metric": "p50/p99 serve latency (ms), Poisson request stream",
+        "value": float(np.percentile(lat, 99)),
+        "unit": "ms (p99)",
+        "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": wall * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{len(reqs)} requests, Poisson {args.serve_rate:g}/s for {args.serve_seconds:g} s: "
+                               "80% singular on grids 512..4096, 20% total on grids 256..1024, 10 m, observer 1.5 m, "
+                               "180 sectors, max distance = grid extent", "requests": len(reqs)},
+        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                       "singular_p50": float(np.percentile(lat_s, 50)), "singular_p99": float(np.percentile(lat_s, 99)),
+                       "total_p50": float(np.percentile(lat_t, 50)) if len(lat_t) else None,
+                       "total_p99": float(np.percentile(lat_t, 99)) if len(lat_t) else None},
+        "served_req_per_s": len(reqs) / wall,
+        "capacity_req_per_s": len(reqs) / wall_f,
+        "plain_one_at_a_time_req_per_s": len(reqs) / plain,
+        "capacity_vs_plain": plain / wall_f,
+        "total_los_evals_per_s_at_capacity": ev_total / wall_f,
+        "server_paced": st, "server_flood": st_f,
+    }
     print(json.dumps(line), flush=True)
 
 

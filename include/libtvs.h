@@ -48,14 +48,15 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 4
+#define TVS_ABI_VERSION 5
 
 enum tvs_status {
     TVS_OK = 0,
     TVS_EINVAL = -1,  /* bad argument: null pointer, size, non-finite value, POV outside the grid */
     TVS_ENOMEM = -2,  /* host or device allocation failed */
     TVS_EDEVICE = -3, /* a HIP call or kernel launch failed (see tvs_last_error) */
-    TVS_ERANGE = -4   /* grid side above 32767 */
+    TVS_ERANGE = -4,  /* grid side above 32767 (or a row longer than the workgroup LDS holds) */
+    TVS_ETIMEDOUT = -5 /* tvs_server_wait: the request did not finish within the timeout */
 };
 
 /* Variant flags. The default, 0, keeps the interpolated elevations in double and decides
@@ -203,6 +204,73 @@ int tvs_batch_destroy(tvs_batch *batch);
  * turn on hip_stream (flags as there). */
 int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,
                              void *hip_stream);
+
+/* ---- Request server: resident grids, continuous batching ------------------------------------
+ * Clients on any thread submit total and singular viewshed requests against grids uploaded once.
+ * A scheduler thread admits total requests in arrival order while their device memory (map plus
+ * scratch, scratch capped at a quarter of the budget) fits hbm_budget_bytes, each on the next of
+ * `streams` streams, so that requests arriving while others run start at once and overlap on the
+ * device; waiting singular requests are launched together, up to max_singular_batch per launch
+ * (one wavefront per line of sight of every query, then one area sum per query). A result does
+ * not depend on what else runs (no atomics, fixed accumulation order). The server is this
+ * library's, not the paper's; the computations are the paper's (Section 4.1, Alg. 1). */
+typedef struct tvs_server tvs_server; /* opaque */
+
+typedef struct tvs_server_config {
+    int64_t hbm_budget_bytes;   /* 0: half the device memory free at creation */
+    int32_t streams;            /* streams for total requests, 0: 4 (at most 16) */
+    int32_t max_singular_batch; /* queries per singular launch, 0: 64 */
+} tvs_server_config;
+
+typedef struct tvs_request_result {
+    int32_t status;      /* TVS_OK, or the failure of this request */
+    int32_t kind;        /* 1 total, 2 singular */
+    double area_m2;      /* singular: the visible area */
+    double latency_ms;   /* submission to completion seen by the scheduler */
+    double queue_ms;     /* submission to launch */
+    int32_t rows, cols;  /* the grid's shape (total: the map's) */
+} tvs_request_result;
+
+typedef struct tvs_server_stats {
+    int32_t grids, pending, running, pad;
+    int64_t completed;
+    int64_t singular_batches;      /* singular launches so far */
+    int64_t singular_batched;      /* singular requests they carried */
+    int64_t max_concurrent_totals; /* most total requests on the device at once */
+    int64_t budget_bytes, bytes_in_use, peak_bytes;
+} tvs_server_stats;
+
+/* Starts a server on the current HIP device (cfg may be NULL for the defaults). */
+int tvs_server_create(const tvs_server_config *cfg, tvs_server **out_server);
+
+/* Uploads a host grid (same rules as tvs_total_viewshed's dem) and returns its id. */
+int tvs_server_add_grid(tvs_server *server, const float *dem, int32_t rows, int32_t cols, double spacing,
+                        int32_t *out_grid_id);
+
+/* Queues a total viewshed of a grid (flags as tvs_total_viewshed_ex, without
+ * TVS_FLAG_COUNT_EVALS); *out_ticket names the request. */
+int tvs_server_submit_total(tvs_server *server, int32_t grid_id, double obs_height, int32_t n_sectors,
+                            double max_dist, uint32_t flags, uint64_t *out_ticket);
+
+/* Queues a singular viewshed (flags: TVS_FLAG_SLOPE_F32, _F64, _EXACT). */
+int tvs_server_submit_singular(tvs_server *server, int32_t grid_id, double obs_height, int32_t n_sectors,
+                               double max_dist, int32_t pov_row, int32_t pov_col, uint32_t flags,
+                               uint64_t *out_ticket);
+
+/* Waits for a request (timeout_ms < 0: no limit; TVS_ETIMEDOUT when it expires) and fills *res. */
+int tvs_server_wait(tvs_server *server, uint64_t ticket, double timeout_ms, tvs_request_result *res);
+
+/* Copies a finished total request's map (rows*cols double) to `out` (host or device) on
+ * hip_stream, and waits for the copy. */
+int tvs_server_copy_map(tvs_server *server, uint64_t ticket, double *out, void *hip_stream);
+
+/* Forgets a finished request and frees its map. */
+int tvs_server_release(tvs_server *server, uint64_t ticket);
+
+int tvs_server_get_stats(tvs_server *server, tvs_server_stats *stats);
+
+/* Finishes every queued request, then stops the scheduler and frees everything. */
+int tvs_server_destroy(tvs_server *server);
 
 /* Shape of the skewed grid of sector `sector` (Section 4.1, Fig. 4b: one row per line of
  * sight): rows t = t0 .. t0 + nrows - 1, columns 0 .. ncols - 1 of the 0..45 deg base frame. */

@@ -17,7 +17,7 @@ __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
     "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "Stats", "Batch", "BatchInfo",
-    "total_viewshed_tiles",
+    "total_viewshed_tiles", "Server",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -32,7 +32,7 @@ FLAG_COUNT_EVALS = 0x20
 FLAG_SLOPE_F32 = 0x40
 FLAG_AUTOTUNE = 0x80
 
-_STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE"}
+_STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE", -5: "TVS_ETIMEDOUT"}
 
 
 class TvsError(RuntimeError):
@@ -69,6 +69,25 @@ class BatchInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerConfig(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("streams", C.c_int32), ("max_singular_batch", C.c_int32)]
+
+
+class RequestResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("kind", C.c_int32), ("area_m2", C.c_double), ("latency_ms", C.c_double),
+                ("queue_ms", C.c_double), ("rows", C.c_int32), ("cols", C.c_int32)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("grids", C.c_int32), ("pending", C.c_int32), ("running", C.c_int32), ("pad", C.c_int32),
+                ("completed", C.c_int64), ("singular_batches", C.c_int64), ("singular_batched", C.c_int64),
+                ("max_concurrent_totals", C.c_int64), ("budget_bytes", C.c_int64), ("bytes_in_use", C.c_int64),
+                ("peak_bytes", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 _lib = None
 i32, f64, u32, vp = C.c_int32, C.c_double, C.c_uint32, C.c_void_p
 
@@ -97,12 +116,24 @@ def lib():
         L.tvs_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
         L.tvs_batch_destroy.argtypes = [vp]
         L.tvs_total_viewshed_tiles.argtypes = [C.POINTER(Tile), i32, i32, u32, vp]
+        u64p = C.POINTER(C.c_uint64)
+        L.tvs_server_create.argtypes = [C.POINTER(ServerConfig), C.POINTER(C.c_void_p)]
+        L.tvs_server_add_grid.argtypes = [vp, vp, i32, i32, f64, C.POINTER(i32)]
+        L.tvs_server_submit_total.argtypes = [vp, i32, f64, i32, f64, u32, u64p]
+        L.tvs_server_submit_singular.argtypes = [vp, i32, f64, i32, f64, i32, i32, u32, u64p]
+        L.tvs_server_wait.argtypes = [vp, C.c_uint64, f64, C.POINTER(RequestResult)]
+        L.tvs_server_copy_map.argtypes = [vp, C.c_uint64, vp, vp]
+        L.tvs_server_release.argtypes = [vp, C.c_uint64]
+        L.tvs_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.tvs_server_destroy.argtypes = [vp]
         L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
                      "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals",
                      "tvs_batch_create", "tvs_batch_run", "tvs_batch_get_info", "tvs_batch_destroy",
-                     "tvs_total_viewshed_tiles"):
+                     "tvs_total_viewshed_tiles", "tvs_server_create", "tvs_server_add_grid",
+                     "tvs_server_submit_total", "tvs_server_submit_singular", "tvs_server_wait",
+                     "tvs_server_copy_map", "tvs_server_release", "tvs_server_get_stats", "tvs_server_destroy"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -300,3 +331,64 @@ def total_viewshed_tiles(tiles, n_sectors: int, flags: int = 0, stream=None):
     max_dist) device tiles, enqueued on ``stream`` or the current stream."""
     arr = _tiles(tiles)
     _check(lib().tvs_total_viewshed_tiles(arr, len(tiles), n_sectors, flags, _stream_handle(stream)))
+
+
+class Server:
+    """A request server (tvs_server_*): resident grids, total and singular requests from any
+    thread, continuous batching on the device. Results come back by ticket."""
+
+    def __init__(self, hbm_budget_bytes: int = 0, streams: int = 0, max_singular_batch: int = 0):
+        cfg = ServerConfig(hbm_budget_bytes, streams, max_singular_batch)
+        h = C.c_void_p()
+        _check(lib().tvs_server_create(C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def add_grid(self, dem, spacing: float) -> int:
+        a = _host_dem(dem)
+        gid = i32()
+        _check(lib().tvs_server_add_grid(self._h, a.ctypes.data_as(vp), a.shape[0], a.shape[1], spacing,
+                                         C.byref(gid)))
+        return gid.value
+
+    def submit_total(self, grid: int, obs_height: float, n_sectors: int, max_dist: float, flags: int = 0) -> int:
+        t = C.c_uint64()
+        _check(lib().tvs_server_submit_total(self._h, grid, obs_height, n_sectors, max_dist, flags, C.byref(t)))
+        return t.value
+
+    def submit_singular(self, grid: int, obs_height: float, n_sectors: int, max_dist: float, pov_row: int,
+                        pov_col: int, flags: int = 0) -> int:
+        t = C.c_uint64()
+        _check(lib().tvs_server_submit_singular(self._h, grid, obs_height, n_sectors, max_dist, pov_row, pov_col,
+                                                flags, C.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> RequestResult:
+        r = RequestResult()
+        _check(lib().tvs_server_wait(self._h, ticket, timeout_ms, C.byref(r)))
+        return r
+
+    def map(self, ticket: int):
+        """The finished total request's map as a host numpy array."""
+        r = self.wait(ticket)
+        out = np.empty((r.rows, r.cols), np.float64)
+        _check(lib().tvs_server_copy_map(self._h, ticket, out.ctypes.data_as(vp), None))
+        return out
+
+    def release(self, ticket: int):
+        _check(lib().tvs_server_release(self._h, ticket))
+
+    def stats(self) -> ServerStats:
+        st = ServerStats()
+        _check(lib().tvs_server_get_stats(self._h, C.byref(st)))
+        return st
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().tvs_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

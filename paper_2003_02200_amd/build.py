@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libtvs.so")
-SOURCES = ["tvs_kernels.hip", "tvs_api.hip", "tvs_batch.hip"]
+SOURCES = ["tvs_kernels.hip", "tvs_api.hip", "tvs_batch.hip", "tvs_server.hip"]
 ARCH = os.environ.get("TVS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -252,7 +252,7 @@ struct Timer {
 // back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
 int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
               uint32_t flags, tvs_stats *stats, hipStream_t st, int debug_sector, uint32_t *d_debugV,
-              int *debug_pitch) {
+              int *debug_pitch, size_t budget = 0) {
     const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
@@ -274,7 +274,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));
     else
         for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
-    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, scratch_budget());
+    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, budget ? budget : scratch_budget());
     size_t maxChunk = 0;
     for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
     const int tabN = std::max(H, W);  // entries for m = 1 .. max(H, W)
@@ -403,6 +403,30 @@ struct DevBuf {
 };
 
 }  // namespace
+
+namespace tvs {
+namespace host {
+
+int total_on_stream(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
+                    uint32_t flags, hipStream_t st, size_t budget) {
+    return run_total(d_dem, H, W, dx, h0, n, R, d_out, flags, nullptr, st, -1, nullptr, nullptr, budget);
+}
+
+size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t flags, size_t budget) {
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
+    const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    std::vector<Sector> S;
+    for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+    size_t maxChunk = 0;
+    for (const Chunk &c : make_chunks(S, elem, pitch_of(H, W), budget ? budget : scratch_budget()))
+        maxChunk = std::max(maxChunk, c.bytes);
+    const size_t tab = (size_t)std::max(H, W) * (sizeof(float2) + sizeof(double2));
+    const size_t kahan = (flags & TVS_FLAG_ACC_KAHAN32) ? (size_t)H * W * 2 * sizeof(float) : 0;
+    return tab + kahan + 256 * 4 + 64 * 8 + maxChunk + 6 * 256;
+}
+
+}  // namespace host
+}  // namespace tvs
 
 extern "C" {
 

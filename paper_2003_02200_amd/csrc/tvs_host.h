@@ -54,6 +54,12 @@ size_t scratch_budget();
 void pool_keep_memory(int dev);
 // Largest LDS a workgroup of this device may request.
 int lds_limit(int dev);
+// The total viewshed's launch sequence on a stream (tvs_total_viewshed_ex without stats); its
+// device scratch is taken stream-ordered and limited to `budget` bytes (0: scratch_budget()).
+int total_on_stream(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
+                    uint32_t flags, hipStream_t st, size_t budget);
+// Device scratch that total_on_stream takes for these arguments.
+size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t flags, size_t budget);
 
 }  // namespace host
 }  // namespace tvs

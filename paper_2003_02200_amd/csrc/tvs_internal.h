@@ -60,6 +60,22 @@ struct BatchTile {
     int32_t pad;
 };
 
+// Singular queries launched together: one entry per (query, sector), and the queries.
+struct SingSec {
+    SecDev s;
+    int32_t query;     // index into the query table
+    int32_t pad;
+};
+struct SingQuery {
+    const float *dem;  // the query's grid (device)
+    int32_t H, W;
+    int32_t pov_i, pov_j;
+    int32_t sec0, nsec;  // its sectors in the SingSec table, in order
+    double h0;
+    float h0f;
+    int32_t pad;
+};
+
 // Launchers (tvs_kernels.hip). All enqueue on `st` and return the launch status.
 hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st);
 hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw,
@@ -82,6 +98,9 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
                               int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st);
 hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
                                  const uint32_t *V, int first, hipStream_t st);
+// Every query's 2 * nsec lines of sight, then each query's area (in sector order).
+hipError_t launch_singular_multi(const SingSec *secs, int nsecs, const SingQuery *qs, int nq, uint32_t *rayV,
+                                 double *areas, bool f64, bool rcp, hipStream_t st);
 size_t sweep_lds_bytes(int maxWx, bool f64);
 constexpr int BATCH_BLOCK = 64;  // cells per side of a back-projection block
 

@@ -810,23 +810,22 @@ __global__ __launch_bounds__(256) void k_backproj_batch(const BatchTile *__restr
 // (renormalised into [0,1) and snapped like Alg. 6's weights). A target is visible iff its
 // slope beats the maximum over all earlier targets: the exclusive wavefront prefix-max of the
 // chunk, combined with the maximum carried from earlier chunks.
+// One line of sight of a singular viewshed, walked by a whole wavefront: sector s of an H x W
+// grid, POV (pov_i, pov_j), direction dir. Returns the packed ring sums (U | e << 30, the POV's
+// own ring included).
 template <typename Tz, bool RCP>
-__global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float *__restrict__ dem,
-                                                  uint32_t *__restrict__ rayV) {
-    const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (ray >= 2 * a.nsec) return;
+__device__ __forceinline__ uint32_t singular_ray(const SecDev &s, int H, int W, const float *__restrict__ dem,
+                                                 Tz h0, int pov_i, int pov_j, int dir) {
     const int lane = threadIdx.x & 63;
-    const SecDev &s = a.s[ray >> 1];
-    const int dir = (ray & 1) ? -1 : 1;
     int Hx, Wx;
-    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    frame_dims(s.kase, H, W, Hx, Wx);
     int p0, q0;
-    to_frame(s.kase, a.W, a.pov_i, a.pov_j, p0, q0);
+    to_frame(s.kase, W, pov_i, pov_j, p0, q0);
     int d0;
     double r0;
     col_offset(s.T, q0, d0, r0);
-    const float zpov = dem[frame_index(s.kase, a.W, p0, q0)];
-    const Tz h = add_rn((Tz)zpov, h0_of<Tz>(a));
+    const float zpov = dem[frame_index(s.kase, W, p0, q0)];
+    const Tz h = add_rn((Tz)zpov, h0);
     const int K = s.K;
     Tz carry = neg_inf<Tz>();
     uint32_t U = 0, e = 0;
@@ -854,8 +853,7 @@ __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float
             const int u = p0 + dd;
             ok = sample_exists(u, dr, Hx);
             if (ok) {
-                const double z64 =
-                    interp(u, dr, Hx, [&](int v) { return dem[frame_index(s.kase, a.W, v, j)]; });
+                const double z64 = interp(u, dr, Hx, [&](int v) { return dem[frame_index(s.kase, W, v, j)]; });
                 const Tz z = (Tz)z64;
                 const Tz dz = sub_rn(z, h);
                 if constexpr (sizeof(Tz) == 4) th = RCP ? __fmul_rn(dz, __fdiv_rn(1.0f, (float)m)) : __fdiv_rn(dz, (float)m);
@@ -874,10 +872,53 @@ __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float
     }
     U = wave_sum_u32(U);
     e = wave_sum_u32(e);
-    if (lane == 0) {
-        if (K >= 1) U += 1u; else e += 1u;  // the POV's own ring
-        rayV[2 * a.k_base + ray] = U | (e << 30);
+    if (K >= 1) U += 1u; else e += 1u;  // the POV's own ring
+    return U | (e << 30);
+}
+
+// One wavefront per line of sight (2 per sector), lanes = 64 consecutive targets. Targets
+// lie on the straight line through the POV: offset d_j - d_q0 rows plus fraction r_j - r_q0
+// (renormalised into [0,1) and snapped like Alg. 6's weights). A target is visible iff its
+// slope beats the maximum over all earlier targets: the exclusive wavefront prefix-max of the
+// chunk, combined with the maximum carried from earlier chunks.
+template <typename Tz, bool RCP>
+__global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float *__restrict__ dem,
+                                                  uint32_t *__restrict__ rayV) {
+    const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ray >= 2 * a.nsec) return;
+    const uint32_t v = singular_ray<Tz, RCP>(a.s[ray >> 1], a.H, a.W, dem, h0_of<Tz>(a), a.pov_i, a.pov_j,
+                                             (ray & 1) ? -1 : 1);
+    if ((threadIdx.x & 63) == 0) rayV[2 * a.k_base + ray] = v;
+}
+
+// Many singular viewsheds in one launch (possibly on different grids): ray r walks sector
+// r / 2 of the table, in direction +1 (r even) or -1 (r odd), for that sector's query.
+template <typename Tz, bool RCP>
+__global__ __launch_bounds__(256) void k_singular_multi(const SingSec *__restrict__ secs, int nsecs,
+                                                        const SingQuery *__restrict__ qs,
+                                                        uint32_t *__restrict__ rayV) {
+    const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (ray >= 2 * nsecs) return;
+    const SingSec &S = secs[ray >> 1];
+    const SingQuery &Q = qs[S.query];
+    const Tz h0 = sizeof(Tz) == 4 ? (Tz)Q.h0f : (Tz)Q.h0;
+    const uint32_t v = singular_ray<Tz, RCP>(S.s, Q.H, Q.W, Q.dem, h0, Q.pov_i, Q.pov_j, (ray & 1) ? -1 : 1);
+    if ((threadIdx.x & 63) == 0) rayV[ray] = v;
+}
+
+// Area of each query of a multi launch: its sectors summed in order, as k_singular_sum does.
+__global__ void k_singular_multi_sum(const SingSec *__restrict__ secs, const SingQuery *__restrict__ qs, int nq,
+                                     const uint32_t *__restrict__ rayV, double *__restrict__ areas) {
+    const int qi = blockIdx.x * blockDim.x + threadIdx.x;
+    if (qi >= nq) return;
+    const SingQuery &Q = qs[qi];
+    double acc = 0.0;
+    for (int k = 0; k < Q.nsec; ++k) {
+        const SecDev &s = secs[Q.sec0 + k].s;
+        const double cv = ring_sum(rayV[2 * (Q.sec0 + k)], s.clip) + ring_sum(rayV[2 * (Q.sec0 + k) + 1], s.clip);
+        acc += s.scale * cv;
     }
+    areas[qi] = acc;
 }
 
 __global__ void k_singular_sum(const ChunkArgs a, const uint32_t *__restrict__ rayV, double *area, int first) {
@@ -1008,6 +1049,19 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
 hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
                                  const uint32_t *V, int first, hipStream_t st) {
     k_backproj_batch<<<nblocks, 256, 0, st>>>(tiles, ntiles, ent, nsec, V, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_singular_multi(const SingSec *secs, int nsecs, const SingQuery *qs, int nq, uint32_t *rayV,
+                                 double *areas, bool f64, bool rcp, hipStream_t st) {
+    const int blocks = (2 * nsecs + 3) / 4;
+    if (f64 && rcp) k_singular_multi<double, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
+    else if (f64) k_singular_multi<double, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
+    else if (rcp) k_singular_multi<float, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
+    else k_singular_multi<float, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_singular_multi_sum<<<(nq + 63) / 64, 64, 0, st>>>(secs, qs, nq, rayV, areas);
     return hipGetLastError();
 }
 

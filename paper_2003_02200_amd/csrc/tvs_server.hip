@@ -1,0 +1,577 @@
+// tvs_server.hip -- a viewshed request server with continuous batching.
+//
+// Grids are uploaded once and stay resident. Clients submit total-viewshed and singular
+// requests from any thread; one scheduler thread owns the device work:
+//  - total requests are admitted in arrival order while their device memory (output map plus
+//    the launch sequence's scratch) fits the HBM budget, each on the next of several streams,
+//    so requests that arrive while others run are started and overlap on the device;
+//  - singular requests that are waiting are launched together: one multi-query ray-scan launch
+//    (every line of sight of every query, one wavefront each) and one per-query area sum, up to a
+//    batch limit, as soon as the previous singular batch has finished;
+//  - completion is read from events recorded after each piece of work; latency runs from
+//    submission to the scheduler seeing that event.
+// Results do not depend on what else runs: every kernel writes its own outputs and accumulates
+// in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/libtvs.h"
+#include "tvs_geom.h"
+#include "tvs_host.h"
+#include "tvs_internal.h"
+
+using namespace tvs;
+using namespace tvs::host;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+double ms_since(Clock::time_point a, Clock::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+struct Grid {
+    float *d = nullptr;
+    int rows = 0, cols = 0;
+    double spacing = 0.0;
+};
+
+enum Kind { KIND_TOTAL = 1, KIND_SINGULAR = 2 };
+enum State { ST_PENDING, ST_RUNNING, ST_DONE };
+
+struct Request {
+    uint64_t ticket = 0;
+    int kind = 0;
+    int dem = 0;
+    double h0 = 0.0, R = 0.0;
+    int n = 0;
+    int pi = 0, pj = 0;
+    uint32_t flags = 0;
+    State state = ST_PENDING;
+    int status = TVS_OK;
+    Clock::time_point t_submit, t_start, t_done;
+    double area = 0.0;
+    double *d_out = nullptr;  // total: the map (server-owned until released)
+    size_t bytes = 0;          // budget held while running
+    int stream = -1;
+    hipEvent_t ev = nullptr;
+    int batch = -1;            // singular: its batch slot
+};
+
+// One launched group of singular queries and its staging memory.
+struct SingBatch {
+    bool busy = false;
+    std::vector<Request *> reqs;
+    hipEvent_t ev = nullptr;
+    size_t cap_secs = 0, cap_q = 0;
+    SingSec *h_secs = nullptr;    // pinned staging
+    SingQuery *h_q = nullptr;
+    double *h_area = nullptr;
+    char *d_mem = nullptr;        // device tables, rays and areas
+    SingSec *d_secs = nullptr;
+    SingQuery *d_q = nullptr;
+    uint32_t *d_rays = nullptr;
+    double *d_area = nullptr;
+};
+
+}  // namespace
+
+struct tvs_server {
+    int dev = 0;
+    size_t budget = 0, used = 0, peak = 0;
+    int nstreams = 4;
+    int max_batch = 64;
+    std::vector<hipStream_t> streams;
+    int next_stream = 0;
+    hipStream_t sing_stream = nullptr;
+    std::vector<Grid> grids;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request *> q_total, q_sing;
+    std::vector<Request *> running;
+    std::unordered_map<uint64_t, Request *> reqs;
+    uint64_t next_ticket = 1;
+    SingBatch sb[2];
+    int64_t n_done = 0, n_batches = 0, n_batched = 0, max_running = 0;
+    bool stop = false;
+    int fatal = TVS_OK;
+    std::thread worker;
+};
+
+namespace {
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Device memory of a total request: its map and the launch sequence's scratch (capped at a
+// quarter of the budget, so that several requests can run side by side).
+size_t total_bytes(const tvs_server *s, const Grid &g, const Request *r) {
+    const size_t cap = std::max(s->budget / 4, (size_t)64 << 20);
+    return align256((size_t)g.rows * g.cols * sizeof(double)) +
+           total_scratch_bytes(g.rows, g.cols, g.spacing, r->n, r->R, r->flags, cap);
+}
+
+int grow_batch(SingBatch &b, size_t secs, size_t nq) {
+    if (secs <= b.cap_secs && nq <= b.cap_q) return TVS_OK;
+    secs = std::max(secs, b.cap_secs * 2);
+    nq = std::max(nq, b.cap_q * 2);
+    if (b.h_secs) (void)hipHostFree(b.h_secs);
+    if (b.h_q) (void)hipHostFree(b.h_q);
+    if (b.h_area) (void)hipHostFree(b.h_area);
+    if (b.d_mem) (void)hipFree(b.d_mem);
+    b.h_secs = nullptr;
+    b.h_q = nullptr;
+    b.h_area = nullptr;
+    b.d_mem = nullptr;
+    b.cap_secs = b.cap_q = 0;
+    HIPCHK(hipHostMalloc((void **)&b.h_secs, secs * sizeof(SingSec), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&b.h_q, nq * sizeof(SingQuery), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void **)&b.h_area, nq * sizeof(double), hipHostMallocDefault));
+    const size_t a = align256(secs * sizeof(SingSec)), q = align256(nq * sizeof(SingQuery)),
+                 rays = align256(2 * secs * sizeof(uint32_t)), ar = align256(nq * sizeof(double));
+    HIPCHK(hipMalloc((void **)&b.d_mem, a + q + rays + ar));
+    b.d_secs = (SingSec *)b.d_mem;
+    b.d_q = (SingQuery *)(b.d_mem + a);
+    b.d_rays = (uint32_t *)(b.d_mem + a + q);
+    b.d_area = (double *)(b.d_mem + a + q + rays);
+    b.cap_secs = secs;
+    b.cap_q = nq;
+    return TVS_OK;
+}
+
+// Launches the waiting singular queries that share the front query's precision (caller holds mu).
+int launch_singular_batch(tvs_server *s, SingBatch &b) {
+    const uint32_t pmask = TVS_FLAG_SLOPE_F32 | TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT;
+    const uint32_t key = s->q_sing.front()->flags & pmask;
+    b.reqs.clear();
+    size_t secs = 0;
+    for (auto it = s->q_sing.begin(); it != s->q_sing.end() && (int)b.reqs.size() < s->max_batch;) {
+        if (((*it)->flags & pmask) == key) {
+            secs += (*it)->n;
+            b.reqs.push_back(*it);
+            it = s->q_sing.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    if (int rc = grow_batch(b, secs, b.reqs.size())) return rc;
+    size_t k0 = 0;
+    for (size_t qi = 0; qi < b.reqs.size(); ++qi) {
+        Request *r = b.reqs[qi];
+        const Grid &g = s->grids[r->dem];
+        SingQuery &Q = b.h_q[qi];
+        memset(&Q, 0, sizeof(Q));
+        Q.dem = g.d;
+        Q.H = g.rows;
+        Q.W = g.cols;
+        Q.pov_i = r->pi;
+        Q.pov_j = r->pj;
+        Q.sec0 = (int32_t)k0;
+        Q.nsec = r->n;
+        Q.h0 = r->h0;
+        Q.h0f = (float)r->h0;
+        for (int k = 0; k < r->n; ++k, ++k0) {
+            const Sector p = plan_sector(k, r->n, g.rows, g.cols, g.spacing, r->R);
+            SingSec &S = b.h_secs[k0];
+            memset(&S, 0, sizeof(S));
+            S.s.T = p.T;
+            S.s.scale = p.scale;
+            S.s.clip = p.clip;
+            S.s.kase = p.kase;
+            S.s.K = p.K;
+            S.s.t0 = p.t0;
+            S.s.nrows = p.nrows;
+            S.query = (int32_t)qi;
+        }
+        r->state = ST_RUNNING;
+        r->t_start = Clock::now();
+        r->batch = (int)(&b - s->sb);
+    }
+    const int nq = (int)b.reqs.size();
+    const bool f64 = (key & TVS_FLAG_SLOPE_F32) == 0;
+    const bool rcp = (key & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
+    hipStream_t st = s->sing_stream;
+    HIPCHK(hipMemcpyAsync(b.d_secs, b.h_secs, secs * sizeof(SingSec), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(b.d_q, b.h_q, nq * sizeof(SingQuery), hipMemcpyHostToDevice, st));
+    HIPCHK(launch_singular_multi(b.d_secs, (int)secs, b.d_q, nq, b.d_rays, b.d_area, f64, rcp, st));
+    HIPCHK(hipMemcpyAsync(b.h_area, b.d_area, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipEventRecord(b.ev, st));
+    b.busy = true;
+    s->n_batches += 1;
+    s->n_batched += nq;
+    return TVS_OK;
+}
+
+void finish(tvs_server *s, Request *r, int status) {
+    r->status = status;
+    r->state = ST_DONE;
+    r->t_done = Clock::now();
+    s->n_done += 1;
+}
+
+void scheduler(tvs_server *s) {
+    (void)hipSetDevice(s->dev);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (true) {
+        bool progress = false;
+        // completions
+        for (size_t x = 0; x < s->running.size();) {
+            Request *r = s->running[x];
+            const hipError_t q = hipEventQuery(r->ev);
+            if (q == hipErrorNotReady) {
+                ++x;
+                continue;
+            }
+            s->used -= r->bytes;
+            r->bytes = 0;
+            finish(s, r, q == hipSuccess ? r->status : TVS_EDEVICE);
+            s->running.erase(s->running.begin() + x);
+            progress = true;
+        }
+        for (SingBatch &b : s->sb) {
+            if (!b.busy) continue;
+            const hipError_t q = hipEventQuery(b.ev);
+            if (q == hipErrorNotReady) continue;
+            for (size_t qi = 0; qi < b.reqs.size(); ++qi) {
+                b.reqs[qi]->area = b.h_area[qi];
+                finish(s, b.reqs[qi], q == hipSuccess ? TVS_OK : TVS_EDEVICE);
+            }
+            b.reqs.clear();
+            b.busy = false;
+            progress = true;
+        }
+        if (progress) s->cv_done.notify_all();
+        if (s->stop && s->q_total.empty() && s->q_sing.empty() && s->running.empty() && !s->sb[0].busy &&
+            !s->sb[1].busy)
+            break;
+        // admission of total requests, in arrival order
+        while (!s->q_total.empty()) {
+            Request *r = s->q_total.front();
+            const Grid &g = s->grids[r->dem];
+            const size_t need = total_bytes(s, g, r);
+            if (!s->running.empty() && s->used + need > s->budget) break;  // wait for memory
+            s->q_total.pop_front();
+            const int si = s->next_stream;
+            s->next_stream = (s->next_stream + 1) % s->nstreams;
+            hipStream_t st = s->streams[si];
+            r->stream = si;
+            r->t_start = Clock::now();
+            r->state = ST_RUNNING;
+            int rc = TVS_OK;
+            if (hipMallocAsync((void **)&r->d_out, (size_t)g.rows * g.cols * sizeof(double), st) != hipSuccess) {
+                (void)hipGetLastError();
+                r->d_out = nullptr;
+                rc = fail(TVS_ENOMEM, "map of %d x %d not available", g.rows, g.cols);
+            }
+            if (rc == TVS_OK)
+                rc = total_on_stream(g.d, g.rows, g.cols, g.spacing, r->h0, r->n, r->R, r->d_out, r->flags, st,
+                                     std::max(s->budget / 4, (size_t)64 << 20));
+            if (rc == TVS_OK && hipEventRecord(r->ev, st) != hipSuccess) rc = TVS_EDEVICE;
+            if (rc != TVS_OK) {
+                finish(s, r, rc);
+                progress = true;
+                continue;
+            }
+            r->bytes = need;
+            s->used += need;
+            s->peak = std::max(s->peak, s->used);
+            s->running.push_back(r);
+            s->max_running = std::max<int64_t>(s->max_running, (int64_t)s->running.size());
+            progress = true;
+        }
+        // singular queries that are waiting: up to two batches in flight (double-buffered
+        // staging); while both are busy, arrivals gather into the next, larger batch
+        if (!s->q_sing.empty()) {
+            for (SingBatch &b : s->sb) {
+                if (b.busy || s->q_sing.empty()) continue;
+                const int rc = launch_singular_batch(s, b);
+                if (rc != TVS_OK) {
+                    for (Request *r : b.reqs) finish(s, r, rc);
+                    b.reqs.clear();
+                    b.busy = false;
+                }
+                progress = true;
+            }
+        }
+        if (progress) {
+            s->cv_done.notify_all();
+            continue;
+        }
+        const bool busy = !s->running.empty() || s->sb[0].busy || s->sb[1].busy;
+        // poll device work every 50 us; sleep until a submission when idle
+        s->cv_work.wait_for(lk, busy ? std::chrono::microseconds(50) : std::chrono::milliseconds(50));
+    }
+}
+
+int check_request(tvs_server *s, int dem, double h0, int n, double R, uint32_t flags, bool total) {
+    if (dem < 0 || dem >= (int)s->grids.size()) return fail(TVS_EINVAL, "unknown grid id %d", dem);
+    const Grid &g = s->grids[dem];
+    if (int rc = check_scalars(g.rows, g.cols, g.spacing, h0, n, R)) return rc;
+    const uint32_t ok = TVS_FLAG_SLOPE_F32 | TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT |
+                        (total ? TVS_FLAG_NO_PRUNE | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_ACC_KAHAN32 : 0u);
+    if (flags & ~ok) return fail(TVS_EINVAL, "unsupported flags 0x%x for this request", flags);
+    if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
+    if (total && sweep_lds_bytes(std::max(g.rows, g.cols), (flags & TVS_FLAG_SLOPE_F32) == 0) + 64 >
+                     (size_t)lds_limit(s->dev))
+        return fail(TVS_ERANGE, "grid %d x %d is too large for the default precision", g.rows, g.cols);
+    return TVS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
+    g_err[0] = 0;
+    if (!out) return fail(TVS_EINVAL, "null out");
+    tvs_server_config c{};
+    if (cfg) c = *cfg;
+    if (c.streams < 0 || c.streams > 16 || c.max_singular_batch < 0 || c.hbm_budget_bytes < 0)
+        return fail(TVS_EINVAL, "streams in [0, 16], max_singular_batch >= 0, hbm_budget_bytes >= 0");
+    tvs_server *s = new (std::nothrow) tvs_server;
+    if (!s) return fail(TVS_ENOMEM, "host memory for the server");
+    auto bail = [&](int rc) {
+        for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
+        if (s->sing_stream) (void)hipStreamDestroy(s->sing_stream);
+        for (SingBatch &b : s->sb)
+            if (b.ev) (void)hipEventDestroy(b.ev);
+        delete s;
+        return rc;
+    };
+    if (hipGetDevice(&s->dev) != hipSuccess) return bail(fail(TVS_EDEVICE, "no current HIP device"));
+    size_t freeb = 0, totalb = 0;
+    (void)hipMemGetInfo(&freeb, &totalb);
+    s->budget = c.hbm_budget_bytes > 0 ? (size_t)c.hbm_budget_bytes : freeb / 2;
+    s->nstreams = c.streams > 0 ? c.streams : 4;
+    s->max_batch = c.max_singular_batch > 0 ? c.max_singular_batch : 64;
+    pool_keep_memory(s->dev);
+    for (int x = 0; x < s->nstreams; ++x) {
+        hipStream_t st;
+        if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
+            return bail(fail(TVS_EDEVICE, "stream creation failed"));
+        s->streams.push_back(st);
+    }
+    if (hipStreamCreateWithFlags(&s->sing_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(TVS_EDEVICE, "stream creation failed"));
+    for (SingBatch &b : s->sb)
+        if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(TVS_EDEVICE, "event creation failed"));
+    s->worker = std::thread(scheduler, s);
+    *out = s;
+    return TVS_OK;
+}
+
+int tvs_server_add_grid(tvs_server *s, const float *dem, int32_t rows, int32_t cols, double spacing,
+                        int32_t *out_id) {
+    g_err[0] = 0;
+    if (!s || !dem || !out_id) return fail(TVS_EINVAL, "null server, dem or out_id");
+    if (int rc = check_scalars(rows, cols, spacing, 0.0, 1, INFINITY)) return rc;
+    if (int rc = check_host_dem(dem, rows, cols)) return rc;
+    Grid g;
+    g.rows = rows;
+    g.cols = cols;
+    g.spacing = spacing;
+    const size_t bytes = (size_t)rows * cols * sizeof(float);
+    if (hipMalloc((void **)&g.d, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TVS_ENOMEM, "grid of %d x %d not available", rows, cols);
+    }
+    if (hipMemcpy(g.d, dem, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(g.d);
+        return fail(TVS_EDEVICE, "grid upload failed");
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out_id = (int32_t)s->grids.size();
+    s->grids.push_back(g);
+    return TVS_OK;
+}
+
+static int submit(tvs_server *s, Request *r, uint64_t *out_ticket) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) {
+        delete r;
+        return fail(TVS_EINVAL, "the server is shutting down");
+    }
+    if (hipEventCreateWithFlags(&r->ev, hipEventDisableTiming) != hipSuccess) {
+        delete r;
+        return fail(TVS_EDEVICE, "event creation failed");
+    }
+    r->ticket = s->next_ticket++;
+    r->t_submit = Clock::now();
+    s->reqs[r->ticket] = r;
+    (r->kind == KIND_TOTAL ? s->q_total : s->q_sing).push_back(r);
+    *out_ticket = r->ticket;
+    s->cv_work.notify_one();
+    return TVS_OK;
+}
+
+int tvs_server_submit_total(tvs_server *s, int32_t grid_id, double obs_height, int32_t n_sectors, double max_dist,
+                            uint32_t flags, uint64_t *out_ticket) {
+    g_err[0] = 0;
+    if (!s || !out_ticket) return fail(TVS_EINVAL, "null server or out_ticket");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (int rc = check_request(s, grid_id, obs_height, n_sectors, max_dist, flags, true)) return rc;
+    }
+    Request *r = new (std::nothrow) Request;
+    if (!r) return fail(TVS_ENOMEM, "host memory");
+    r->kind = KIND_TOTAL;
+    r->dem = grid_id;
+    r->h0 = obs_height;
+    r->n = n_sectors;
+    r->R = max_dist;
+    r->flags = flags;
+    return submit(s, r, out_ticket);
+}
+
+int tvs_server_submit_singular(tvs_server *s, int32_t grid_id, double obs_height, int32_t n_sectors,
+                               double max_dist, int32_t pov_row, int32_t pov_col, uint32_t flags,
+                               uint64_t *out_ticket) {
+    g_err[0] = 0;
+    if (!s || !out_ticket) return fail(TVS_EINVAL, "null server or out_ticket");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (int rc = check_request(s, grid_id, obs_height, n_sectors, max_dist, flags, false)) return rc;
+        const Grid &g = s->grids[grid_id];
+        if (pov_row < 0 || pov_row >= g.rows || pov_col < 0 || pov_col >= g.cols)
+            return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, g.rows, g.cols);
+    }
+    Request *r = new (std::nothrow) Request;
+    if (!r) return fail(TVS_ENOMEM, "host memory");
+    r->kind = KIND_SINGULAR;
+    r->dem = grid_id;
+    r->h0 = obs_height;
+    r->n = n_sectors;
+    r->R = max_dist;
+    r->pi = pov_row;
+    r->pj = pov_col;
+    r->flags = flags;
+    return submit(s, r, out_ticket);
+}
+
+int tvs_server_wait(tvs_server *s, uint64_t ticket, double timeout_ms, tvs_request_result *res) {
+    g_err[0] = 0;
+    if (!s || !res) return fail(TVS_EINVAL, "null server or result");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(ticket);
+    if (it == s->reqs.end()) return fail(TVS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request *r = it->second;
+    auto done = [&] { return r->state == ST_DONE; };
+    if (timeout_ms < 0) s->cv_done.wait(lk, done);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double, std::milli>(timeout_ms), done))
+        return fail(TVS_ETIMEDOUT, "request %llu not finished", (unsigned long long)ticket);
+    memset(res, 0, sizeof(*res));
+    res->status = r->status;
+    res->kind = r->kind;
+    res->area_m2 = r->area;
+    res->latency_ms = ms_since(r->t_submit, r->t_done);
+    res->queue_ms = ms_since(r->t_submit, r->t_start);
+    res->rows = s->grids[r->dem].rows;
+    res->cols = s->grids[r->dem].cols;
+    return TVS_OK;
+}
+
+int tvs_server_copy_map(tvs_server *s, uint64_t ticket, double *out, void *hip_stream) {
+    g_err[0] = 0;
+    if (!s || !out) return fail(TVS_EINVAL, "null server or out");
+    double *src = nullptr;
+    size_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return fail(TVS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        Request *r = it->second;
+        if (r->kind != KIND_TOTAL || r->state != ST_DONE || r->status != TVS_OK || !r->d_out)
+            return fail(TVS_EINVAL, "ticket %llu holds no finished map", (unsigned long long)ticket);
+        src = r->d_out;
+        bytes = (size_t)s->grids[r->dem].rows * s->grids[r->dem].cols * sizeof(double);
+    }
+    HIPCHK(hipMemcpyAsync(out, src, bytes, hipMemcpyDefault, (hipStream_t)hip_stream));
+    HIPCHK(hipStreamSynchronize((hipStream_t)hip_stream));
+    return TVS_OK;
+}
+
+int tvs_server_release(tvs_server *s, uint64_t ticket) {
+    g_err[0] = 0;
+    if (!s) return fail(TVS_EINVAL, "null server");
+    Request *r = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->reqs.find(ticket);
+        if (it == s->reqs.end()) return fail(TVS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        if (it->second->state != ST_DONE) return fail(TVS_EINVAL, "request %llu still running",
+                                                      (unsigned long long)ticket);
+        r = it->second;
+        s->reqs.erase(it);
+    }
+    if (r->d_out) (void)hipFreeAsync(r->d_out, s->streams[std::max(r->stream, 0)]);
+    if (r->ev) (void)hipEventDestroy(r->ev);
+    delete r;
+    return TVS_OK;
+}
+
+int tvs_server_get_stats(tvs_server *s, tvs_server_stats *st) {
+    g_err[0] = 0;
+    if (!s || !st) return fail(TVS_EINVAL, "null server or stats");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(st, 0, sizeof(*st));
+    st->grids = (int32_t)s->grids.size();
+    st->pending = (int32_t)(s->q_total.size() + s->q_sing.size());
+    st->running = (int32_t)s->running.size() + (int32_t)(s->sb[0].reqs.size() + s->sb[1].reqs.size());
+    st->completed = s->n_done;
+    st->singular_batches = s->n_batches;
+    st->singular_batched = s->n_batched;
+    st->max_concurrent_totals = s->max_running;
+    st->budget_bytes = (int64_t)s->budget;
+    st->bytes_in_use = (int64_t)s->used;
+    st->peak_bytes = (int64_t)s->peak;
+    return TVS_OK;
+}
+
+int tvs_server_destroy(tvs_server *s) {
+    g_err[0] = 0;
+    if (!s) return TVS_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv_work.notify_all();
+    }
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipDeviceSynchronize();
+    for (auto &kv : s->reqs) {
+        Request *r = kv.second;
+        if (r->d_out) (void)hipFreeAsync(r->d_out, s->streams[std::max(r->stream, 0)]);
+        if (r->ev) (void)hipEventDestroy(r->ev);
+        delete r;
+    }
+    for (SingBatch &b : s->sb) {
+        if (b.ev) (void)hipEventDestroy(b.ev);
+        if (b.h_secs) (void)hipHostFree(b.h_secs);
+        if (b.h_q) (void)hipHostFree(b.h_q);
+        if (b.h_area) (void)hipHostFree(b.h_area);
+        if (b.d_mem) (void)hipFree(b.d_mem);
+    }
+    for (Grid &g : s->grids) (void)hipFree(g.d);
+    for (hipStream_t st : s->streams) {
+        (void)hipStreamSynchronize(st);
+        (void)hipStreamDestroy(st);
+    }
+    if (s->sing_stream) (void)hipStreamDestroy(s->sing_stream);
+    delete s;
+    return TVS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,156 @@
+"""The request server (tvs_server_*): continuous batching of singular and total requests on
+resident grids; every result must equal the same request computed alone (marked `gpu`)."""
+import math
+import sys
+import threading
+
+import numpy as np
+import pytest
+
+from synth import fractal_dem
+
+pytestmark = pytest.mark.gpu
+P_DEFAULT = 65
+
+
+def note(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def tvs():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    import paper_2003_02200_amd as t
+
+    t.lib()
+    return t
+
+
+GRIDS = [(64, 64, 10.0), (37, 150, 10.0), (200, 90, 5.0), (1, 1, 10.0), (128, 128, 10.0), (90, 33, 7.5)]
+
+
+def _grids():
+    return [fractal_dem(max(H, W), 300 + x, 0.6, 1200.0)[:H, :W].copy() for x, (H, W, _) in enumerate(GRIDS)]
+
+
+def _requests(seed, count, frac_singular=0.75):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for _ in range(count):
+        g = int(rng.integers(0, len(GRIDS)))
+        H, W, dx = GRIDS[g]
+        h0 = float(rng.uniform(1.5, 30.0))
+        n = int(rng.choice([8, 24, 180]))
+        R = float(rng.choice([math.inf, max(H, W) * dx, 300.0]))
+        flags = int(rng.choice([0, 0, 0x40, 0x8]))
+        if rng.uniform() < frac_singular:
+            reqs.append(("s", g, h0, n, R, int(rng.integers(0, H)), int(rng.integers(0, W)), flags))
+        else:
+            reqs.append(("t", g, h0, n, R, flags))
+    return reqs
+
+
+def _alone(tvs, dems, r):
+    if r[0] == "s":
+        _, g, h0, n, R, i, j, flags = r
+        return tvs.singular_viewshed(dems[g], GRIDS[g][2], h0, n, R, i, j, flags=flags)
+    _, g, h0, n, R, flags = r
+    return tvs.total_viewshed(dems[g], GRIDS[g][2], h0, n, R, flags=flags)
+
+
+def _submit(srv, ids, r):
+    if r[0] == "s":
+        _, g, h0, n, R, i, j, flags = r
+        return srv.submit_singular(ids[g], h0, n, R, i, j, flags)
+    _, g, h0, n, R, flags = r
+    return srv.submit_total(ids[g], h0, n, R, flags)
+
+
+def _check_all(tvs, srv, dems, reqs, tickets):
+    for r, t in zip(reqs, tickets):
+        res = srv.wait(t, 60000.0)
+        assert res.status == 0, r
+        want = _alone(tvs, dems, r)
+        if r[0] == "s":
+            assert res.area_m2 == want, r  # bit for bit: the same kernels, the same summation order
+        else:
+            np.testing.assert_array_equal(srv.map(t), want, err_msg=str(r))
+        assert res.latency_ms >= res.queue_ms >= 0.0
+        srv.release(t)
+
+
+@pytest.mark.parametrize("budget", [0, 1 << 20])
+def test_mixed_requests_equal_alone(tvs, budget):
+    """Requests from two client threads, mixed kinds, sizes and precisions; with the default
+    budget totals overlap, with a 1 MB budget they run one at a time: results are the same."""
+    dems = _grids()
+    srv = tvs.Server(hbm_budget_bytes=budget, streams=4, max_singular_batch=16)
+    ids = [srv.add_grid(d, GRIDS[x][2]) for x, d in enumerate(dems)]
+    reqs = _requests(7 if budget else 8, 60)
+    tickets = [None] * len(reqs)
+
+    def client(lo, hi):
+        for x in range(lo, hi):
+            tickets[x] = _submit(srv, ids, reqs[x])
+
+    note(f"server mix budget={budget}")
+    th = threading.Thread(target=client, args=(30, 60))
+    th.start()
+    client(0, 30)
+    th.join()
+    _check_all(tvs, srv, dems, reqs, tickets)
+    st = srv.stats()
+    print(f"server budget={budget}: {st.as_dict()}", flush=True)
+    assert st.completed == len(reqs) and st.pending == 0 and st.running == 0 and st.bytes_in_use == 0
+    if budget:
+        assert st.max_concurrent_totals == 1
+    srv.close()
+
+
+def test_singular_queries_are_batched_and_match_oracle(tvs, orc):
+    dems = _grids()
+    srv = tvs.Server(max_singular_batch=64)
+    ids = [srv.add_grid(d, GRIDS[x][2]) for x, d in enumerate(dems)]
+    rng = np.random.default_rng(3)
+    reqs = []
+    for _ in range(200):
+        g = int(rng.integers(0, len(GRIDS)))
+        H, W, dx = GRIDS[g]
+        reqs.append(("s", g, 1.5, 24, max(H, W) * dx, int(rng.integers(0, H)), int(rng.integers(0, W)), 0))
+    note("server singular burst")
+    tickets = [_submit(srv, ids, r) for r in reqs]
+    for r, t in list(zip(reqs, tickets))[:20]:
+        _, g, h0, n, R, i, j, _f = r
+        o = orc.singular(dems[g], GRIDS[g][2], h0, n, R, i, j, prec=P_DEFAULT)
+        assert srv.wait(t).area_m2 == pytest.approx(o["area"], rel=1e-12)
+    _check_all(tvs, srv, dems, reqs, tickets)
+    st = srv.stats()
+    print(f"singular burst: {st.singular_batches} launches for {st.singular_batched} queries", flush=True)
+    assert st.singular_batched == 200 and st.singular_batches < 200
+    srv.close()
+
+
+def test_server_rejects_bad_requests(tvs):
+    srv = tvs.Server()
+    gid = srv.add_grid(np.zeros((8, 9), np.float32), 10.0)
+    with pytest.raises(tvs.TvsError):
+        srv.submit_total(gid + 1, 1.5, 8, 100.0)
+    with pytest.raises(tvs.TvsError):
+        srv.submit_singular(gid, 1.5, 8, 100.0, 8, 0)
+    with pytest.raises(tvs.TvsError):
+        srv.submit_total(gid, 1.5, 8, 100.0, flags=tvs.FLAG_COUNT_EVALS)
+    with pytest.raises(tvs.TvsError):
+        srv.submit_singular(gid, 1.5, 8, 100.0, 0, 0, flags=tvs.FLAG_SWEEP_SCAN)
+    with pytest.raises(tvs.TvsError):
+        srv.add_grid(np.full((3, 3), np.nan, np.float32), 10.0)
+    with pytest.raises(tvs.TvsError):
+        srv.wait(12345)
+    t = srv.submit_total(gid, 1.5, 8, 100.0)
+    assert srv.wait(t).status == 0
+    srv.release(t)
+    with pytest.raises(tvs.TvsError):
+        srv.release(t)
+    srv.close()
