@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 5
+#define TVS_ABI_VERSION 6
 
 enum tvs_status {
     TVS_OK = 0,
@@ -117,8 +117,14 @@ int tvs_total_viewshed(const float *dem, int32_t rows, int32_t cols, double spac
                        double obs_height, int32_t n_sectors, double max_dist, double *out);
 
 /* Singular viewshed, Alg. 1: the area (m^2) visible from grid cell (pov_row, pov_col), each
- * line of sight passing through the POV. Host pointers. `out_mask` must be NULL (the per-cell
- * mask is not provided by this version; a non-NULL mask returns TVS_EINVAL). */
+ * line of sight passing through the POV. Host pointers. `out_mask` (nullable, rows*cols u8)
+ * receives the visibility of every cell (the boolean map of Section 1; Alg. 1 itself returns the
+ * area only): a cell at offset (di, dj) from the POV belongs to half-sector q, the one whose
+ * interval (beta_{q-1}, beta_q] of direction angles, beta_q = (2q + 1) pi / 2n measured like the
+ * sector axes, holds it (cos(beta) di - sin(beta) dj > 0 above a boundary, with cos and sin
+ * computed in double); its ring index along that line of sight is
+ * m = floor(sqrt(di^2 + dj^2) cos(s') + 1e-9); it is visible iff m = 0, or m is a target of the
+ * line of sight (m <= its last target, m < rho) and that target is visible. */
 int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing,
                           double obs_height, int32_t n_sectors, double max_dist,
                           int32_t pov_row, int32_t pov_col, double *out_area, uint8_t *out_mask);
@@ -130,8 +136,8 @@ int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, dou
                              double obs_height, int32_t n_sectors, double max_dist,
                              double *d_out, void *hip_stream);
 
-/* Device-resident singular viewshed: *d_area (device double) receives the area; d_mask must
- * be NULL. */
+/* Device-resident singular viewshed: *d_area (device double) receives the area; d_mask
+ * (nullable, device rows*cols u8) the visibility mask as in tvs_singular_viewshed. */
 int tvs_singular_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
                                 double obs_height, int32_t n_sectors, double max_dist,
                                 int32_t pov_row, int32_t pov_col, double *d_area, uint8_t *d_mask,
@@ -151,6 +157,16 @@ int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, dou
                              double obs_height, int32_t n_sectors, double max_dist,
                              int32_t pov_row, int32_t pov_col, uint32_t flags, double *d_area,
                              uint32_t *d_ray_V, void *hip_stream);
+
+/* Multiple (cumulative) viewshed: d_count[i*cols + j] (device u32) = how many of the npov
+ * POVs see cell (i, j), each POV's visibility as tvs_singular_viewshed's mask; d_areas (nullable,
+ * device npov doubles) receives each POV's singular area. povs is a host array of npov
+ * (row, col) pairs, read before return. All lines of sight of all POVs run in one launch, then one
+ * launch computes every cell. Flags: TVS_FLAG_SLOPE_F32, _F64, _EXACT. */
+int tvs_multiple_viewshed(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                          double obs_height, int32_t n_sectors, double max_dist, const int32_t *povs,
+                          int32_t npov, uint32_t flags, uint32_t *d_count, double *d_areas,
+                          void *hip_stream);
 
 /* ---- Batches of independent tiles (uneven sizes) -------------------------------------------
  * Every tile is an independent total viewshed (tvs_total_viewshed_async semantics) with its own

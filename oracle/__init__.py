@@ -60,6 +60,10 @@ def lib():
                                  C.c_void_p, C.c_void_p, C.c_void_p, C.c_longlong,
                                  C.POINTER(C.c_longlong), C.POINTER(C.c_double), C.POINTER(C.c_uint32),
                                  C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.oracle_multiple.argtypes = [f32p, C.c_int, C.c_int, C.c_double, C.c_double, C.c_int, C.c_double,
+                                      C.c_int, i32p, C.c_int, u32p]
+        L.oracle_half_sector.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.oracle_half_sector.restype = C.c_int
         L.oracle_los_evals.argtypes = [C.c_int, C.c_int, C.c_double, C.c_int, C.c_double,
                                        C.POINTER(C.c_longlong), C.POINTER(C.c_longlong)]
         _lib = L
@@ -139,6 +143,21 @@ def singular(dem, spacing, obs_height, n, max_dist, i0, j0, prec=64):
                                _ptr(U), _ptr(e), _ptr(cv))
     _check(rc, "singular")
     return dict(area=area.value, U=U, e=e, cv=cv)
+
+
+def multiple(dem, spacing, obs_height, n, max_dist, povs, prec=64):
+    """Multiple viewshed: per cell, how many of the POVs [(row, col), ...] see it (u32 map);
+    with one POV, that POV's visibility mask."""
+    dem = _dem(dem)
+    H, W = dem.shape
+    p = np.ascontiguousarray(np.asarray(povs, np.int32).reshape(-1, 2))
+    out = np.zeros((H, W), np.uint32)
+    _check(lib().oracle_multiple(dem, H, W, spacing, obs_height, n, max_dist, prec, p, len(p), out), "multiple")
+    return out
+
+
+def half_sector(n, di, dj):
+    return lib().oracle_half_sector(n, di, dj)
 
 
 def ray(dem, spacing, obs_height, n, max_dist, k, mode, t_or_p0, q0, delta, prec=64, cap=None):

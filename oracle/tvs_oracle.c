@@ -500,6 +500,121 @@ int oracle_singular(const float *dem, int rows, int cols, double dx, double h0, 
     return ORC_OK;
 }
 
+/* Singular visibility mask (reading R18 in the design notes; Alg. 1 returns only the area, the
+ * problem statement of Section 1 speaks of a boolean map). A grid cell at offset (di, dj) from
+ * the POV belongs to half-sector q (axis angle q*pi/n, q < n forward of sector q, q >= n backward
+ * of sector q - n) whose angular interval (beta_{q-1}, beta_q] holds its direction, where
+ * beta_q = (2q + 1) pi / (2n): the cross product cos(beta) di - sin(beta) dj is > 0 above a
+ * boundary and <= 0 on or below it. Its ring index along that line of sight is
+ * m = floor(sqrt(di^2 + dj^2) cos(s') + 1e-9) (index units, snapped like the skew offsets). It is
+ * visible iff m = 0, or m is a target of that line of sight (m <= the last target) and that
+ * target is visible. The search below simply tries every half-sector. */
+static int mask_half_sector(int di, int dj, int n, const double *cb, const double *sb)
+{
+    for (int q = 0; q < 2 * n; q++) {
+        int ql = (q + 2 * n - 1) % (2 * n);
+        double up = cb[q] * (double)di - sb[q] * (double)dj;
+        double lo = cb[ql] * (double)di - sb[ql] * (double)dj;
+        if (up <= 0.0 && lo > 0.0) return q;
+    }
+    return -1;
+}
+
+/* Ring visibility of the 2n singular lines of sight from (i0, j0): vis[r * cap + m - 1] for target
+ * m of ray r = 2k (forward) or 2k + 1 (backward), and each ray's last target in M[r]. */
+static int singular_rays(const float *dem, const sector_t *S, int n, int i0, int j0, double h0, int prec,
+                         unsigned char *vis, long long cap, long long *M)
+{
+    for (int k = 0; k < n; k++) {
+        const sector_t *s = &S[k];
+        long long p0, q0;
+        to_base(s, i0, j0, &p0, &q0);
+        double zp = X_at(dem, s, p0, q0);
+        double h64;
+        float h32;
+        pov_height(zp, h0, &h64, &h32);
+        ray_t a = walk(dem, s, 1, p0, q0, +1, h64, h32, prec, vis + (size_t)(2 * k) * cap, NULL, NULL, cap);
+        ray_t b = walk(dem, s, 1, p0, q0, -1, h64, h32, prec, vis + (size_t)(2 * k + 1) * cap, NULL, NULL, cap);
+        M[2 * k] = a.M;
+        M[2 * k + 1] = b.M;
+    }
+    return ORC_OK;
+}
+
+static int cell_visible(int di, int dj, int n, const sector_t *S, const double *cb, const double *sb,
+                        const unsigned char *vis, long long cap, const long long *M)
+{
+    if (di == 0 && dj == 0) return 1;
+    int q = mask_half_sector(di, dj, n, cb, sb);
+    if (q < 0) return 0;
+    int k = q % n;
+    int ray = 2 * k + (q >= n ? 1 : 0);
+    double c = cos(S[k].sp);
+    double t = sqrt((double)di * (double)di + (double)dj * (double)dj) * c;
+    long long m = (long long)floor(t + 1e-9);
+    if (m == 0) return 1;
+    if (m > M[ray] || !((double)m < S[k].rho)) return 0;
+    return vis[(size_t)ray * cap + (size_t)(m - 1)] ? 1 : 0;
+}
+
+/* Multiple (cumulative) viewshed: count[i][j] = number of the npov POVs (pov[2p], pov[2p+1])
+ * whose singular mask holds cell (i, j); with npov = 1 it is the mask itself. */
+int oracle_multiple(const float *dem, int rows, int cols, double dx, double h0, int n, double R, int prec,
+                    const int *pov, int npov, uint32_t *count)
+{
+    int rc = check_args(dem, rows, cols, dx, h0, n, R);
+    if (rc) return rc;
+    if (!count || !pov || npov < 1 || (prec != 32 && prec != 33 && prec != 64 && prec != 65)) return ORC_EINVAL;
+    for (int p = 0; p < npov; p++)
+        if (pov[2 * p] < 0 || pov[2 * p] >= rows || pov[2 * p + 1] < 0 || pov[2 * p + 1] >= cols) return ORC_EINVAL;
+    sector_t *S = make_sectors(rows, cols, dx, n, R);
+    if (!S) return ORC_ENOMEM;
+    long long cap = (rows > cols ? rows : cols) + 1;
+    double *cb = malloc(sizeof(double) * 2 * (size_t)n);
+    double *sb = malloc(sizeof(double) * 2 * (size_t)n);
+    unsigned char *vis = malloc((size_t)2 * n * (size_t)cap);
+    long long *M = malloc(sizeof(long long) * 2 * (size_t)n);
+    if (!cb || !sb || !vis || !M) {
+        free(cb); free(sb); free(vis); free(M); free_sectors(S, n);
+        return ORC_ENOMEM;
+    }
+    for (int q = 0; q < 2 * n; q++) {
+        double beta = (M_PI * (double)(2 * q + 1)) / (double)(2 * n);
+        cb[q] = cos(beta);
+        sb[q] = sin(beta);
+    }
+    memset(count, 0, sizeof(uint32_t) * (size_t)rows * cols);
+    for (int p = 0; p < npov; p++) {
+        int i0 = pov[2 * p], j0 = pov[2 * p + 1];
+        memset(vis, 0, (size_t)2 * n * (size_t)cap);
+        singular_rays(dem, S, n, i0, j0, h0, prec, vis, cap, M);
+        #pragma omp parallel for schedule(static)
+        for (int i = 0; i < rows; i++)
+            for (int j = 0; j < cols; j++)
+                count[(size_t)i * cols + j] += (uint32_t)cell_visible(i - i0, j - j0, n, S, cb, sb, vis, cap, M);
+    }
+    free(cb); free(sb); free(vis); free(M);
+    free_sectors(S, n);
+    return ORC_OK;
+}
+
+/* The half-sector of offset (di, dj) (-1 for the POV itself), for tests of the assignment. */
+int oracle_half_sector(int n, int di, int dj)
+{
+    if (n < 1 || (di == 0 && dj == 0)) return -1;
+    double *cb = malloc(sizeof(double) * 2 * (size_t)n);
+    double *sb = malloc(sizeof(double) * 2 * (size_t)n);
+    if (!cb || !sb) { free(cb); free(sb); return -2; }
+    for (int q = 0; q < 2 * n; q++) {
+        double beta = (M_PI * (double)(2 * q + 1)) / (double)(2 * n);
+        cb[q] = cos(beta);
+        sb[q] = sin(beta);
+    }
+    int q = mask_half_sector(di, dj, n, cb, sb);
+    free(cb); free(sb);
+    return q;
+}
+
 /* One line of sight in detail, for tests: mode 0 = skewed row t through column q0;
  * mode 1 = singular through base cell (t_or_p0, q0). Fills up to cap entries of
  * per-target visibility, slope and interpolated elevation; returns the number of

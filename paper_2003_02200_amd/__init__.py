@@ -17,7 +17,7 @@ __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
     "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "Stats", "Batch", "BatchInfo",
-    "total_viewshed_tiles", "Server",
+    "total_viewshed_tiles", "Server", "multiple_viewshed", "singular_mask",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -126,6 +126,7 @@ def lib():
         L.tvs_server_release.argtypes = [vp, C.c_uint64]
         L.tvs_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.tvs_server_destroy.argtypes = [vp]
+        L.tvs_multiple_viewshed.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp, i32, u32, vp, vp, vp]
         L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
@@ -133,7 +134,8 @@ def lib():
                      "tvs_batch_create", "tvs_batch_run", "tvs_batch_get_info", "tvs_batch_destroy",
                      "tvs_total_viewshed_tiles", "tvs_server_create", "tvs_server_add_grid",
                      "tvs_server_submit_total", "tvs_server_submit_singular", "tvs_server_wait",
-                     "tvs_server_copy_map", "tvs_server_release", "tvs_server_get_stats", "tvs_server_destroy"):
+                     "tvs_server_copy_map", "tvs_server_release", "tvs_server_get_stats", "tvs_server_destroy",
+                     "tvs_multiple_viewshed"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -235,6 +237,44 @@ def singular_viewshed(dem, spacing: float, obs_height: float, n_sectors: int, ma
     if rays:
         return a, rv.cpu().numpy().view(np.uint32).copy()
     return a
+
+
+def singular_mask(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float, pov_row: int,
+                  pov_col: int):
+    """(area, mask): the singular viewshed's area and its per-cell visibility (uint8 0/1), host
+    arrays (tvs_singular_viewshed with a mask)."""
+    a = _host_dem(dem)
+    H, W = a.shape
+    area = C.c_double()
+    mask = np.empty((H, W), np.uint8)
+    _check(lib().tvs_singular_viewshed(a.ctypes.data_as(vp), H, W, spacing, obs_height, n_sectors, max_dist,
+                                       pov_row, pov_col, C.byref(area), mask.ctypes.data_as(vp)))
+    return area.value, mask
+
+
+def multiple_viewshed(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float, povs, flags: int = 0,
+                      stream=None, areas: bool = False):
+    """Per cell, how many of the POVs [(row, col), ...] see it (uint32 map; a device tensor for a
+    device dem, else numpy). With ``areas=True`` also each POV's singular area."""
+    import torch
+
+    d = dem if _is_torch_cuda(dem) else torch.from_numpy(_host_dem(dem)).cuda()
+    if d.dtype != torch.float32 or d.dim() != 2:
+        raise ValueError("dem must be a 2-D float32 grid")
+    d = d.contiguous()
+    H, W = d.shape
+    p = np.ascontiguousarray(np.asarray(povs, np.int32).reshape(-1, 2))
+    cnt = torch.empty((H, W), dtype=torch.int32, device=d.device)
+    ar = torch.empty(len(p), dtype=torch.float64, device=d.device)
+    with torch.cuda.device(d.device):
+        _check(lib().tvs_multiple_viewshed(C.c_void_p(d.data_ptr()), H, W, spacing, obs_height, n_sectors, max_dist,
+                                           p.ctypes.data_as(vp), len(p), flags, C.c_void_p(cnt.data_ptr()),
+                                           C.c_void_p(ar.data_ptr()), _stream_handle(stream)))
+    if _is_torch_cuda(dem):
+        return (cnt, ar) if areas else cnt
+    torch.cuda.current_stream(d.device).synchronize() if stream is None else stream.synchronize()
+    c = cnt.cpu().numpy().view(np.uint32).copy()
+    return (c, ar.cpu().numpy()) if areas else c
 
 
 def sector_shape(rows: int, cols: int, n_sectors: int, sector: int):

@@ -53,6 +53,7 @@ Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
     else if (4 * num == den) s.T = 1.0;
     else s.T = tan(sp);
     const double c = cos(sp);
+    s.c = c;
     s.scale = (M_PI / (2.0 * (double)n)) * (dx * dx) / (c * c);
     s.K = TVS_K_UNBOUNDED;
     s.clip = 0.0;
@@ -393,6 +394,110 @@ int run_singular(const float *d_dem, int H, int W, double dx, double h0, int n, 
     return TVS_OK;
 }
 
+// Singular lines of sight of npov POVs on one grid in one launch, then their areas (d_areas,
+// nullable) and the visibility mask of POV 0 (d_mask) or the multiple viewshed (d_count). The
+// tables are uploaded before return; the kernels are enqueued on st.
+int run_multi(const float *d_dem, int H, int W, double dx, double h0, int n, double R, const int32_t *povs,
+              int npov, uint32_t flags, double *d_areas, uint8_t *d_mask, uint32_t *d_count, hipStream_t st) {
+    const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
+    const bool rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    pool_keep_memory(dev);
+    std::vector<Sector> S;
+    for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+    std::vector<SingSec> secs((size_t)npov * n);
+    std::vector<SingQuery> qs(npov);
+    for (int p = 0; p < npov; ++p) {
+        SingQuery &Q = qs[p];
+        std::memset(&Q, 0, sizeof(Q));
+        Q.dem = d_dem;
+        Q.H = H;
+        Q.W = W;
+        Q.pov_i = povs[2 * p];
+        Q.pov_j = povs[2 * p + 1];
+        Q.sec0 = p * n;
+        Q.nsec = n;
+        Q.h0 = h0;
+        Q.h0f = (float)h0;
+        for (int k = 0; k < n; ++k) {
+            SingSec &E = secs[(size_t)p * n + k];
+            std::memset(&E, 0, sizeof(E));
+            E.s.T = S[k].T;
+            E.s.scale = S[k].scale;
+            E.s.clip = S[k].clip;
+            E.s.kase = S[k].kase;
+            E.s.K = S[k].K;
+            E.s.t0 = S[k].t0;
+            E.s.nrows = S[k].nrows;
+            E.query = p;
+        }
+    }
+    // half-sector boundary directions (2q + 1) pi / 2n and the sectors' cos s', rho
+    std::vector<double> geo(6 * (size_t)n);
+    for (int q = 0; q < 2 * n; ++q) {
+        const double beta = (M_PI * (double)(2 * q + 1)) / (double)(2 * n);
+        geo[q] = cos(beta);
+        geo[2 * n + q] = sin(beta);
+    }
+    for (int k = 0; k < n; ++k) {
+        geo[4 * n + k] = S[k].c;
+        geo[5 * n + k] = S[k].rho;
+    }
+    const int L = std::max(H, W);
+    const int words = 2 * ((L + 63) / 64 + 1);
+    const size_t nr = (size_t)2 * npov * n;
+    const bool want_cells = d_mask || d_count;
+    auto a256 = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_secs = a256(secs.size() * sizeof(SingSec)), b_q = a256(qs.size() * sizeof(SingQuery)),
+                 b_pov = a256((size_t)2 * npov * sizeof(int32_t)), b_geo = a256(geo.size() * sizeof(double)),
+                 b_rays = a256(nr * sizeof(uint32_t)), b_bits = want_cells ? a256(nr * words * sizeof(uint32_t)) : 0,
+                 b_ml = want_cells ? a256(nr * sizeof(int32_t)) : 0,
+                 b_area = d_areas ? 0 : a256((size_t)npov * sizeof(double));
+    Scratch scr;
+    scr.st = st;
+    if (hipMallocAsync(&scr.p, b_secs + b_q + b_pov + b_geo + b_rays + b_bits + b_ml + b_area, st) != hipSuccess) {
+        (void)hipGetLastError();
+        scr.p = nullptr;
+        return fail(TVS_ENOMEM, "device scratch for %d singular viewsheds not available", npov);
+    }
+    char *base = (char *)scr.p;
+    SingSec *d_secs = (SingSec *)base;
+    SingQuery *d_q = (SingQuery *)(base += b_secs);
+    int32_t *d_pov = (int32_t *)(base += b_q);
+    double *d_geo = (double *)(base += b_pov);
+    uint32_t *d_rays = (uint32_t *)(base += b_geo);
+    uint32_t *d_bits = want_cells ? (uint32_t *)(base + b_rays) : nullptr;
+    int32_t *d_ml = want_cells ? (int32_t *)(base + b_rays + b_bits) : nullptr;
+    double *areas = d_areas ? d_areas : (double *)(base + b_rays + b_bits + b_ml);
+    HIPCHK(hipMemcpyAsync(d_secs, secs.data(), secs.size() * sizeof(SingSec), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_q, qs.data(), qs.size() * sizeof(SingQuery), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_pov, povs, (size_t)2 * npov * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));  // the host tables may go out of scope
+    HIPCHK(launch_singular_multi(d_secs, npov * n, d_q, npov, d_rays, areas, f64, rcp, st, d_bits, words, d_ml));
+    if (want_cells) {
+        MaskArgs m;
+        std::memset(&m, 0, sizeof(m));
+        m.H = H;
+        m.W = W;
+        m.n = n;
+        m.npov = d_mask ? 1 : npov;
+        m.pov = d_pov;
+        m.cb = d_geo;
+        m.sb = d_geo + 2 * n;
+        m.ck = d_geo + 4 * n;
+        m.rho = d_geo + 5 * n;
+        m.bits = d_bits;
+        m.mlast = d_ml;
+        m.words = words;
+        m.mask = d_mask;
+        m.count = d_count;
+        HIPCHK(launch_mask_multi(m, st));
+    }
+    return TVS_OK;
+}
+
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
@@ -495,9 +600,38 @@ int tvs_singular_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, dou
 int tvs_singular_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
                                 int32_t n_sectors, double max_dist, int32_t pov_row, int32_t pov_col,
                                 double *d_area, uint8_t *d_mask, void *hip_stream) {
-    if (d_mask) return fail(TVS_EINVAL, "the per-cell singular mask is not provided; pass NULL");
-    return tvs_singular_viewshed_ex(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col,
-                                    0u, d_area, nullptr, hip_stream);
+    if (!d_mask)
+        return tvs_singular_viewshed_ex(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row,
+                                        pov_col, 0u, d_area, nullptr, hip_stream);
+    g_err[0] = 0;
+    if (!d_dem || !d_area) return fail(TVS_EINVAL, "null dem or area pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
+        return fail(TVS_EINVAL, "POV (%d, %d) outside the %d x %d grid", pov_row, pov_col, rows, cols);
+    const int32_t pov[2] = {pov_row, pov_col};
+    return run_multi(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, pov, 1, 0u, d_area, d_mask, nullptr,
+                     (hipStream_t)hip_stream);
+}
+
+int tvs_multiple_viewshed(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                          int32_t n_sectors, double max_dist, const int32_t *povs, int32_t npov, uint32_t flags,
+                          uint32_t *d_count, double *d_areas, void *hip_stream) {
+    g_err[0] = 0;
+    if (!d_dem || !povs || !d_count) return fail(TVS_EINVAL, "null dem, povs or count pointer");
+    if (npov < 1 || npov > (1 << 20)) return fail(TVS_EINVAL, "npov must be in [1, 2^20]");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    for (int p = 0; p < npov; ++p)
+        if (povs[2 * p] < 0 || povs[2 * p] >= rows || povs[2 * p + 1] < 0 || povs[2 * p + 1] >= cols)
+            return fail(TVS_EINVAL, "POV %d (%d, %d) outside the %d x %d grid", p, povs[2 * p], povs[2 * p + 1], rows,
+                        cols);
+    if (flags & ~(TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F32))
+        return fail(TVS_EINVAL, "unsupported flags 0x%x for the multiple viewshed", flags);
+    if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
+        return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
+    return run_multi(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, povs, npov, flags, d_areas, nullptr,
+                     d_count, (hipStream_t)hip_stream);
 }
 
 int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double spacing, double obs_height,
@@ -505,7 +639,6 @@ int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double s
                           uint8_t *out_mask) {
     g_err[0] = 0;
     if (!dem || !out_area) return fail(TVS_EINVAL, "null dem or area pointer");
-    if (out_mask) return fail(TVS_EINVAL, "the per-cell singular mask is not provided; pass NULL");
     int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
     if (rc) return rc;
     if (pov_row < 0 || pov_row >= rows || pov_col < 0 || pov_col >= cols)
@@ -514,16 +647,24 @@ int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double s
     const size_t N = (size_t)rows * cols;
     DevBuf<float> d_dem;
     DevBuf<double> d_area;
-    if (d_dem.alloc(N) != hipSuccess || d_area.alloc(1) != hipSuccess) {
+    DevBuf<uint8_t> d_mask;
+    if (d_dem.alloc(N) != hipSuccess || d_area.alloc(1) != hipSuccess || (out_mask && d_mask.alloc(N) != hipSuccess)) {
         (void)hipGetLastError();
         return fail(TVS_ENOMEM, "device buffers for a %d x %d grid not available", rows, cols);
     }
     HIPCHK(hipMemcpy(d_dem.p, dem, N * sizeof(float), hipMemcpyHostToDevice));
-    rc = run_singular(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, 0u, d_area.p,
-                      nullptr, nullptr);
+    if (out_mask) {
+        const int32_t pov[2] = {pov_row, pov_col};
+        rc = run_multi(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, pov, 1, 0u, d_area.p, d_mask.p,
+                       nullptr, nullptr);
+    } else {
+        rc = run_singular(d_dem.p, rows, cols, spacing, obs_height, n_sectors, max_dist, pov_row, pov_col, 0u,
+                          d_area.p, nullptr, nullptr);
+    }
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(nullptr));
     HIPCHK(hipMemcpy(out_area, d_area.p, sizeof(double), hipMemcpyDeviceToHost));
+    if (out_mask) HIPCHK(hipMemcpy(out_mask, d_mask.p, N, hipMemcpyDeviceToHost));
     return TVS_OK;
 }
 

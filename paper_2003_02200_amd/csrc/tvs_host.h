@@ -27,6 +27,7 @@ int fail(int code, const char *fmt, ...);
 struct Sector {
     int kase, Hx, Wx;
     double T;      // tan s'
+    double c;      // cos s'
     double rho;    // max_dist cos s' / spacing
     int K;         // last target index in range (TVS_K_UNBOUNDED when max_dist never binds)
     double scale;  // (pi / 2n) spacing^2 / cos^2 s'

@@ -98,9 +98,26 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
                               int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st);
 hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
                                  const uint32_t *V, int first, hipStream_t st);
-// Every query's 2 * nsec lines of sight, then each query's area (in sector order).
+// Every query's 2 * nsec lines of sight, then each query's area (in sector order). With `bits`
+// non-null also each ray's per-target visibility (`words` u32 per ray) and last target index.
 hipError_t launch_singular_multi(const SingSec *secs, int nsecs, const SingQuery *qs, int nq, uint32_t *rayV,
-                                 double *areas, bool f64, bool rcp, hipStream_t st);
+                                 double *areas, bool f64, bool rcp, hipStream_t st, uint32_t *bits = nullptr,
+                                 int words = 0, int32_t *mlast = nullptr);
+// Mask / multiple viewshed over one grid from the rays of npov singular queries.
+struct MaskArgs {
+    int32_t H, W, n, npov;
+    const int32_t *pov;     // 2 * npov (row, col)
+    const double *cb, *sb;  // cos / sin of the 2n half-sector boundary angles (2q + 1) pi / 2n
+    const double *ck;       // cos s' of the n sectors
+    const double *rho;      // max_dist cos s' / spacing of the n sectors (inf if unbounded)
+    const uint32_t *bits;   // per ray, `words` u32 of target visibility
+    const int32_t *mlast;   // per ray, last target index
+    int32_t words;
+    int32_t pad;
+    uint8_t *mask;          // nullable: 0/1 per cell
+    uint32_t *count;        // nullable: POVs that see the cell
+};
+hipError_t launch_mask_multi(const MaskArgs &a, hipStream_t st);
 size_t sweep_lds_bytes(int maxWx, bool f64);
 constexpr int BATCH_BLOCK = 64;  // cells per side of a back-projection block
 

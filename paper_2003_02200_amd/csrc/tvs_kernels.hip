@@ -813,9 +813,13 @@ __global__ __launch_bounds__(256) void k_backproj_batch(const BatchTile *__restr
 // One line of sight of a singular viewshed, walked by a whole wavefront: sector s of an H x W
 // grid, POV (pov_i, pov_j), direction dir. Returns the packed ring sums (U | e << 30, the POV's
 // own ring included).
+// With `bits` non-null it also records the visibility of every target (bit m - 1 of the ray's
+// u32 words) and, in *mlast, the last target index of the line of sight.
 template <typename Tz, bool RCP>
 __device__ __forceinline__ uint32_t singular_ray(const SecDev &s, int H, int W, const float *__restrict__ dem,
-                                                 Tz h0, int pov_i, int pov_j, int dir) {
+                                                 Tz h0, int pov_i, int pov_j, int dir,
+                                                 uint32_t *__restrict__ bits = nullptr,
+                                                 int32_t *__restrict__ mlast = nullptr) {
     const int lane = threadIdx.x & 63;
     int Hx, Wx;
     frame_dims(s.kase, H, W, Hx, Wx);
@@ -863,12 +867,22 @@ __device__ __forceinline__ uint32_t singular_ray(const SecDev &s, int H, int W, 
         // existence is monotone along the line of sight, so the valid lanes form a prefix
         const Tz incl = wave_prefix_max(th);
         const Tz excl = vmax(carry, wave_shift_up(neg_inf<Tz>(), incl));
-        if (ok && th > excl) {
+        const bool vis = ok && th > excl;
+        if (vis) {
             if (m < K) U += (uint32_t)(2 * m + 1);
             else e += 1;
         }
         carry = vmax(carry, lane63(incl));
-        if (!__all(ok)) break;
+        const unsigned long long okm = __ballot(ok);
+        if (bits) {
+            const unsigned long long vm = __ballot(vis);
+            if (lane == 0) {
+                bits[2 * (m0 >> 6)] = (uint32_t)vm;
+                bits[2 * (m0 >> 6) + 1] = (uint32_t)(vm >> 32);
+                *mlast = m0 + __popcll(okm);
+            }
+        }
+        if (okm != ~0ull) break;
     }
     U = wave_sum_u32(U);
     e = wave_sum_u32(e);
@@ -896,14 +910,72 @@ __global__ __launch_bounds__(256) void k_singular(const ChunkArgs a, const float
 template <typename Tz, bool RCP>
 __global__ __launch_bounds__(256) void k_singular_multi(const SingSec *__restrict__ secs, int nsecs,
                                                         const SingQuery *__restrict__ qs,
-                                                        uint32_t *__restrict__ rayV) {
+                                                        uint32_t *__restrict__ rayV, uint32_t *__restrict__ bits,
+                                                        int words, int32_t *__restrict__ mlast) {
     const int ray = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (ray >= 2 * nsecs) return;
     const SingSec &S = secs[ray >> 1];
     const SingQuery &Q = qs[S.query];
     const Tz h0 = sizeof(Tz) == 4 ? (Tz)Q.h0f : (Tz)Q.h0;
-    const uint32_t v = singular_ray<Tz, RCP>(S.s, Q.H, Q.W, Q.dem, h0, Q.pov_i, Q.pov_j, (ray & 1) ? -1 : 1);
+    const uint32_t v = singular_ray<Tz, RCP>(S.s, Q.H, Q.W, Q.dem, h0, Q.pov_i, Q.pov_j, (ray & 1) ? -1 : 1,
+                                             bits ? bits + (int64_t)ray * words : nullptr,
+                                             bits ? mlast + ray : nullptr);
     if ((threadIdx.x & 63) == 0) rayV[ray] = v;
+}
+
+// Visibility mask / multiple viewshed from the singular lines of sight of npov POVs on one grid
+// (query p's sectors are p * n .. p * n + n - 1 of the multi launch). Cell offset (di, dj) from
+// a POV falls in half-sector q, the one whose interval (beta_{q-1}, beta_q] of direction angles
+// holds it (beta_q = (2q + 1) pi / 2n; cos(beta) di - sin(beta) dj is > 0 above a boundary): a
+// first guess from atan2, then settled by those boundary tests alone. Its ring index is
+// m = floor(sqrt(di^2 + dj^2) cos s' + 1e-9) on that half-sector's line of sight; it is visible
+// iff m = 0, or m is a target (m <= the last one, m < rho) and that target is visible.
+__global__ __launch_bounds__(256) void k_mask_multi(MaskArgs a) {
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    const int n2 = 2 * a.n;
+    uint32_t cnt = 0;
+    for (int p = 0; p < a.npov; ++p) {
+        const int di = i - a.pov[2 * p], dj = j - a.pov[2 * p + 1];
+        if (di == 0 && dj == 0) {
+            ++cnt;
+            continue;
+        }
+        const double fdi = (double)di, fdj = (double)dj;
+        double phi = atan2(fdi, fdj);
+        if (phi < 0.0) phi += 2.0 * M_PI;
+        int q = (int)floor(phi * (double)a.n / M_PI + 0.5);
+        q = ((q % n2) + n2) % n2;
+        for (int it = 0; it < 4; ++it) {
+            const double up = __dsub_rn(__dmul_rn(a.cb[q], fdi), __dmul_rn(a.sb[q], fdj));
+            if (up > 0.0) {
+                q = q + 1 == n2 ? 0 : q + 1;
+                continue;
+            }
+            const int ql = q == 0 ? n2 - 1 : q - 1;
+            const double lo = __dsub_rn(__dmul_rn(a.cb[ql], fdi), __dmul_rn(a.sb[ql], fdj));
+            if (!(lo > 0.0)) {
+                q = ql;
+                continue;
+            }
+            break;
+        }
+        const int k = q % a.n;
+        const int ray = 2 * (p * a.n + k) + (q >= a.n ? 1 : 0);
+        const double t = __dmul_rn(__dsqrt_rn(__dadd_rn(__dmul_rn(fdi, fdi), __dmul_rn(fdj, fdj))), a.ck[k]);
+        const int64_t m = (int64_t)floor(__dadd_rn(t, 1e-9));
+        if (m == 0) {
+            ++cnt;
+            continue;
+        }
+        if (m > a.mlast[ray] || !((double)m < a.rho[k])) continue;
+        const uint32_t w = a.bits[(int64_t)ray * a.words + ((m - 1) >> 5)];
+        cnt += (w >> ((m - 1) & 31)) & 1u;
+    }
+    const int64_t cell = (int64_t)i * a.W + j;
+    if (a.count) a.count[cell] = cnt;
+    if (a.mask) a.mask[cell] = (uint8_t)(cnt != 0);
 }
 
 // Area of each query of a multi launch: its sectors summed in order, as k_singular_sum does.
@@ -1053,15 +1125,22 @@ hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks
 }
 
 hipError_t launch_singular_multi(const SingSec *secs, int nsecs, const SingQuery *qs, int nq, uint32_t *rayV,
-                                 double *areas, bool f64, bool rcp, hipStream_t st) {
+                                 double *areas, bool f64, bool rcp, hipStream_t st, uint32_t *bits, int words,
+                                 int32_t *mlast) {
     const int blocks = (2 * nsecs + 3) / 4;
-    if (f64 && rcp) k_singular_multi<double, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
-    else if (f64) k_singular_multi<double, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
-    else if (rcp) k_singular_multi<float, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
-    else k_singular_multi<float, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV);
+    if (f64 && rcp) k_singular_multi<double, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV, bits, words, mlast);
+    else if (f64) k_singular_multi<double, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV, bits, words, mlast);
+    else if (rcp) k_singular_multi<float, true><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV, bits, words, mlast);
+    else k_singular_multi<float, false><<<blocks, 256, 0, st>>>(secs, nsecs, qs, rayV, bits, words, mlast);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_singular_multi_sum<<<(nq + 63) / 64, 64, 0, st>>>(secs, qs, nq, rayV, areas);
+    return hipGetLastError();
+}
+
+hipError_t launch_mask_multi(const MaskArgs &a, hipStream_t st) {
+    const dim3 grid((a.W + 63) / 64, (a.H + 3) / 4);
+    k_mask_multi<<<grid, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 

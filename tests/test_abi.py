@@ -93,11 +93,20 @@ def test_rejects_bad_grid(tvs):
     area = C.c_double(7.0)
     assert L.tvs_singular_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, 2, 0, C.byref(area),
                                    None) == -1
-    mask = np.zeros(4, np.uint8)
-    assert L.tvs_singular_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, 0, 0, C.byref(area),
+    mask = np.full(4, 9, np.uint8)
+    assert L.tvs_singular_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, 0, 5, C.byref(area),
                                    mask.ctypes.data_as(vp)) == -1
-    assert area.value == 7.0  # outputs untouched on error
-    assert b"mask" in L.tvs_last_error()
+    assert area.value == 7.0 and np.all(mask == 9)  # outputs untouched on error
+    assert b"POV" in L.tvs_last_error()
+    povs = np.array([0, 0, 1, 2], np.int32)  # second POV outside the 2 x 2 grid
+    cnt = np.zeros(4, np.uint32)
+    L.tvs_multiple_viewshed.argtypes = [vp, C.c_int32, C.c_int32, C.c_double, C.c_double, C.c_int32, C.c_double, vp,
+                                        C.c_int32, C.c_uint32, vp, vp, vp]
+    assert L.tvs_multiple_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, povs.ctypes.data_as(vp), 2, 0,
+                                   cnt.ctypes.data_as(vp), None, None) == -1
+    assert b"POV 1" in L.tvs_last_error()
+    assert L.tvs_multiple_viewshed(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, povs.ctypes.data_as(vp), 0, 0,
+                                   cnt.ctypes.data_as(vp), None, None) == -1
 
 
 @pytest.mark.parametrize("H,W,n,R", [(37, 53, 7, math.inf), (1, 1, 3, 5.0), (64, 17, 180, 300.0),

@@ -493,3 +493,51 @@ def test_workload_4000_precision_study(tvs, orc):
               f"p99 rel {np.quantile(rel, 0.99):.3g}; crop vs oracle max rel {relc.max():.3g}", flush=True)
         assert rel[~fd].max() <= (1e-5 if "kahan32" in name else 1e-10)
         assert fl / pairs <= (1e-5 if name.startswith("default") else 1e-2)
+
+
+@pytest.mark.parametrize("H,W,n,R,pov", [(41, 41, 8, INF, (20, 5)), (64, 80, 36, 300.0, (0, 0)),
+                                         (150, 120, 180, 1000.0, (75, 60)), (1, 1, 3, INF, (0, 0)),
+                                         (90, 33, 24, 250.0, (89, 32)), (57, 200, 12, INF, (30, 199))])
+def test_singular_mask_bitexact(tvs, orc, H, W, n, R, pov):
+    """The visibility mask of a singular viewshed equals the oracle's cell by cell, and the area
+    equals the plain singular path's."""
+    dem = fractal_dem(max(H, W), 23, 0.6, 700.0)[:H, :W].copy()
+    note(f"singular mask H={H} W={W} n={n} R={R} pov={pov}")
+    area, mask = tvs.singular_mask(dem, 10.0, 1.5, n, R, *pov)
+    want = orc.multiple(dem, 10.0, 1.5, n, R, [pov], prec=P_DEFAULT).astype(np.uint8)
+    bad = np.argwhere(mask != want)
+    assert bad.size == 0, f"{len(bad)} cells differ, first {bad[:5].tolist()}"
+    assert area == tvs.singular_viewshed(dem, 10.0, 1.5, n, R, *pov)
+    assert area == pytest.approx(orc.singular(dem, 10.0, 1.5, n, R, *pov, prec=P_DEFAULT)["area"], rel=1e-12)
+
+
+@pytest.mark.parametrize("flags,prec", MODES)
+def test_multiple_viewshed_bitexact(tvs, orc, flags, prec):
+    dem = fractal_dem(170, 29, 0.6, 900.0)[:150].copy()
+    rng = np.random.default_rng(11)
+    povs = [(int(rng.integers(0, 150)), int(rng.integers(0, 170))) for _ in range(10)] + [(0, 0), (149, 169)]
+    note(f"multiple viewshed flags={flags}")
+    cnt, areas = tvs.multiple_viewshed(dem, 10.0, 1.5, 36, 900.0, povs, flags=flags, areas=True)
+    want = orc.multiple(dem, 10.0, 1.5, 36, 900.0, povs, prec=prec)
+    assert np.array_equal(cnt, want)
+    for p, a in zip(povs, areas):
+        assert a == pytest.approx(orc.singular(dem, 10.0, 1.5, 36, 900.0, *p, prec=prec)["area"], rel=1e-12)
+
+
+def test_multiple_viewshed_workload_2000(tvs, orc):
+    """Ten random POVs accumulated on the 2000 x 2000 workload (the shape of the paper's GIS
+    comparison, Section 5.3): the whole count map against the oracle."""
+    import torch
+
+    w = WORKLOADS["tvs2000"]
+    dem = workload_dem("tvs2000")
+    rng = np.random.default_rng(2020)
+    povs = [(int(rng.integers(0, 2000)), int(rng.integers(0, 2000))) for _ in range(10)]
+    note("multiple viewshed tvs2000, 10 POVs")
+    d = torch.from_numpy(dem).cuda()
+    cnt = tvs.multiple_viewshed(d, w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"], povs)
+    torch.cuda.synchronize()
+    want = orc.multiple(dem, w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"], povs, prec=P_DEFAULT)
+    got = cnt.cpu().numpy().view(np.uint32)
+    assert np.array_equal(got, want)
+    print(f"tvs2000 multiple viewshed: {int((want > 0).sum())} cells seen by at least one of 10 POVs", flush=True)

@@ -547,3 +547,87 @@ def test_double_reciprocal_decisions_match_quotient(orc):
         pairs += int(v.sum())
         assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["e"], b["e"])
     assert pairs > 20000
+
+
+# ------------------------------------------------------------------ singular mask and multiple viewshed
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 12, 180])
+def test_half_sector_is_the_nearest_axis(orc, n):
+    """Each cell offset is assigned the half-sector whose axis direction q pi / n (q >= n: the
+    backward axes) is nearest to it: within half a sector, and the only one when not on a
+    boundary (an independent nearest-axis reading of the assignment)."""
+    for di in range(-23, 24):
+        for dj in range(-23, 24):
+            if di == 0 and dj == 0:
+                assert orc.half_sector(n, di, dj) == -1
+                continue
+            q = orc.half_sector(n, di, dj)
+            assert 0 <= q < 2 * n
+            phi = math.atan2(di, dj) % (2 * math.pi)
+            dist = [abs((phi - x * math.pi / n + math.pi) % (2 * math.pi) - math.pi) for x in range(2 * n)]
+            half = math.pi / (2 * n)
+            assert dist[q] <= half + 1e-12
+            if dist[q] < half - 1e-9:
+                assert min(d for x, d in enumerate(dist) if x != q) > half
+
+
+def test_mask_flat_disc(orc):
+    """Flat ground, observer above it: every target is visible, so the mask is the disc of ring
+    indices below rho: all cells nearer than R - 1 cell are visible, none farther than
+    R / cos(pi / 2n) + 1 cells, and the count is close to pi R^2."""
+    dem = flat(81, 81, 25.0)
+    n, R = 36, 300.0
+    m = orc.multiple(dem, 10.0, 1.5, n, R, [(40, 40)]).astype(bool)
+    ii, jj = np.mgrid[0:81, 0:81]
+    d = np.hypot(ii - 40, jj - 40)
+    assert m[d < R / 10.0 - 1].all()
+    assert not m[d > R / 10.0 / math.cos(math.pi / (2 * n)) + 1].any()
+    assert abs(m.sum() - math.pi * 30.0 ** 2) < 0.05 * math.pi * 30.0 ** 2
+
+
+def test_mask_wall_shadow(orc):
+    """A tall wall across the line of sight at 0 deg hides every cell behind it on that line and
+    nothing in front of it or on the other side."""
+    dem = flat(41, 41, 0.0)
+    dem[15:26, 10] = 100.0
+    m = orc.multiple(dem, 10.0, 1.5, 8, INF, [(20, 5)]).astype(bool)
+    assert m[20, :11].all()      # up to and including the wall
+    assert not m[20, 11:].any()  # behind it
+    assert m[20, 5] and m[5:36, 5].all()
+
+
+def test_mask_on_axis_cells_follow_the_ray(orc):
+    """Cells on the axis directions of n = 4 (0, 45, 90, 135 deg and backward) take the visibility
+    of the ray target at their index, read through the independent per-ray walk."""
+    dem = fractal_dem(33, 12, 0.6, 400.0)
+    i0, j0 = 14, 17
+    n = 4
+    mask = orc.multiple(dem, 10.0, 1.5, n, INF, [(i0, j0)]).astype(bool)
+    dirs = {0: (0, 1), 1: (1, 1), 2: (1, 0), 3: (1, -1)}
+    for k, (si, sj) in dirs.items():
+        for delta in (1, -1):
+            info = orc.sector_info(33, 33, 10.0, n, INF, k)
+            # the singular ray of sector k through the POV, in its base frame
+            if info["case"] == 0:
+                p0, q0 = i0, j0
+            elif info["case"] == 1:
+                p0, q0 = j0, i0
+            elif info["case"] == 2:
+                p0, q0 = 33 - 1 - j0, i0
+            else:
+                p0, q0 = i0, 33 - 1 - j0
+            r = orc.ray(dem, 10.0, 1.5, n, INF, k, 1, p0, q0, delta)
+            for m in range(1, r["M"] + 1):
+                # axis k points at k pi / n from +column toward +row
+                i, j = i0 + delta * si * m, j0 + delta * sj * m
+                if 0 <= i < 33 and 0 <= j < 33:
+                    assert mask[i, j] == r["vis"][m - 1], (k, delta, m)
+
+
+def test_multiple_is_the_sum_of_masks(orc):
+    dem = fractal_dem(40, 4, 0.6, 600.0)[:37].copy()
+    povs = [(3, 4), (20, 20), (36, 0), (0, 39), (20, 20)]
+    tot = orc.multiple(dem, 10.0, 2.0, 24, 250.0, povs)
+    acc = sum(orc.multiple(dem, 10.0, 2.0, 24, 250.0, [p]).astype(np.int64) for p in povs)
+    assert np.array_equal(tot, acc)
+    assert tot[20, 20] == 2 and tot.max() <= len(povs)
