@@ -1008,7 +1008,6 @@ __global__ void k_singular_sum(const ChunkArgs a, const uint32_t *__restrict__ r
 
 // ------------------------------------------------------------------------------ launchers
 
-constexpr int SWEEP_WAVES = 4;
 
 size_t sweep_lds_bytes(int maxWx, bool f64) {
     // row with sentinels, then the per-block suffix and prefix maxima of the early exit
@@ -1044,12 +1043,39 @@ static hipError_t set_lds(F f, size_t bytes) {
 template <typename Tz>
 static hipError_t sweep_go(void (*f)(ChunkArgs, const Tz *, uint32_t *, const typename Tab<Tz>::type *,
                                      unsigned long long *),
-                           dim3 grid, size_t lds, hipStream_t st, const ChunkArgs &a, const void *skw, uint32_t *V,
-                           const typename Tab<Tz>::type *tab, unsigned long long *work) {
+                           int nw, dim3 grid, size_t lds, hipStream_t st, const ChunkArgs &a, const void *skw,
+                           uint32_t *V, const typename Tab<Tz>::type *tab, unsigned long long *work) {
     hipError_t e = set_lds(f, lds);
     if (e != hipSuccess) return e;
-    f<<<grid, 64 * SWEEP_WAVES, lds, st>>>(a, (const Tz *)skw, V, tab, work);
+    f<<<grid, 64 * nw, lds, st>>>(a, (const Tz *)skw, V, tab, work);
     return hipGetLastError();
+}
+
+template <int NW>
+static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void *skw, uint32_t *V,
+                           const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
+                           unsigned long long *work, hipStream_t st) {
+    if (f64) {
+        auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
+                 : rcp ? (prune ? k_sweep<double, NW, true, true> : k_sweep<double, NW, true, false>)
+                       : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
+        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+    }
+    auto f = scan ? (rcp ? k_sweep_scan<float, NW, true> : k_sweep_scan<float, NW, false>)
+                  : rcp ? (prune ? k_sweep<float, NW, true, true> : k_sweep<float, NW, true, false>)
+                        : (prune ? k_sweep<float, NW, false, true> : k_sweep<float, NW, false, false>);
+    return sweep_go<float>(f, NW, grid, lds, st, a, skw, V, tab32, work);
+}
+
+// Waves per sweep workgroup: a workgroup holds one row in LDS, so long rows leave room for few
+// workgroups per CU; more waves per workgroup keep about 32 waves per CU busy (4 for rows up to
+// ~2600 double samples, 8 and 16 beyond).
+int sweep_waves(size_t lds) {
+    const size_t per_cu = 160 * 1024;
+    const size_t groups = std::max<size_t>(1, per_cu / std::max<size_t>(lds + 64, 1));
+    if (groups >= 8) return 4;
+    if (groups >= 4) return 8;
+    return 16;
 }
 
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
@@ -1057,17 +1083,11 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
                         unsigned long long *work, hipStream_t st) {
     const dim3 grid(maxRows, a.nsec);
     const size_t lds = sweep_lds_bytes(maxWx, f64);
-    constexpr int NW = SWEEP_WAVES;
-    if (f64) {
-        auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
-                 : rcp ? (prune ? k_sweep<double, NW, true, true> : k_sweep<double, NW, true, false>)
-                       : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
-        return sweep_go<double>(f, grid, lds, st, a, skw, V, tab64, work);
+    switch (sweep_waves(lds)) {
+    case 4: return sweep_nw<4>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    case 8: return sweep_nw<8>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    default: return sweep_nw<16>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
     }
-    auto f = scan ? (rcp ? k_sweep_scan<float, NW, true> : k_sweep_scan<float, NW, false>)
-                  : rcp ? (prune ? k_sweep<float, NW, true, true> : k_sweep<float, NW, true, false>)
-                        : (prune ? k_sweep<float, NW, false, true> : k_sweep<float, NW, false, false>);
-    return sweep_go<float>(f, grid, lds, st, a, skw, V, tab32, work);
 }
 
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum, float *kahan_c,

@@ -163,6 +163,9 @@ WORKLOADS = {
     # 4000x4000 fractal + 6 Gaussian ridges, 0-3000 m, 5 m, 1.5 m, 360 sectors, 10 km
     "tvs4000": dict(side=4000, seed=3, roughness=0.55, zmax=3000.0, spacing=5.0, obs_height=1.5,
                     n_sectors=360, max_dist=10000.0, ridge_seed=33),
+    # 8000x8000 fractal, 0-3000 m, 10 m, 1.5 m, 180 sectors, 10 km (the largest grid shape of Table 2)
+    "tvs8000": dict(side=8000, seed=6, roughness=0.55, zmax=3000.0, spacing=10.0, obs_height=1.5,
+                    n_sectors=180, max_dist=10000.0),
 }
 
 

@@ -69,6 +69,8 @@ SHAPES = [
     (300, 17, 9, 2000.0, "int"),
     (130, 70, 180, 700.0, "fractal"),
     (45, 45, 4, 300.0, "plane"),
+    (9, 6000, 3, 2000.0, "fractal"),   # rows long enough for 16 waves per sweep workgroup
+    (3000, 9, 4, 1500.0, "int"),       # 8 waves per workgroup on the transposed axes
 ]
 
 
