@@ -702,7 +702,19 @@ __device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W
     }
     const int ilast = min(i0 + BP_T, H) - 1, jlast = min(j0 + BP_T, W) - 1;
     for (int k = 0; k < nsec; ++k) {
-        const SecDev &s = sec(k);
+        // the sector's parameters, once per sector in scalar registers
+        SecDev s;
+        {
+            const SecDev &g = sec(k);
+            s.T = g.T;
+            s.scale = g.scale;
+            s.clip = g.clip;
+            s.off = g.off;
+            s.kase = __builtin_amdgcn_readfirstlane(g.kase);
+            s.K = g.K;
+            s.t0 = __builtin_amdgcn_readfirstlane(g.t0);
+            s.nrows = g.nrows;
+        }
         // the block's base-frame rectangle [plo, phi] x [qlo, qhi]
         int plo, phi, qlo, qhi;
         switch (s.kase) {
@@ -726,9 +738,24 @@ __device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W
             col_d[threadIdx.x] = d;
             col_r[threadIdx.x] = r;
         }
-        if (lane < nq) {
-            const uint32_t *src = V + s.off + (int64_t)rbase * pitch + qlo + lane;
-            for (int rr = wv; rr < nr; rr += 4) tile[rr * BP_LP + lane] = src[(int64_t)rr * pitch];
+        {
+            // rows are staged in rounds of 12 per wavefront, each round's loads all in flight
+            // before its LDS stores
+            constexpr int RND = 12;
+            const uint32_t *src = V + s.off + (int64_t)rbase * pitch + qlo + min(lane, nq - 1);
+            for (int r0 = wv; r0 < nr; r0 += 4 * RND) {
+                uint32_t v[RND];
+#pragma unroll
+                for (int x = 0; x < RND; ++x) {
+                    const int rr = r0 + 4 * x;
+                    if (rr < nr) v[x] = src[(int64_t)rr * pitch];
+                }
+#pragma unroll
+                for (int x = 0; x < RND; ++x) {
+                    const int rr = r0 + 4 * x;
+                    if (rr < nr && lane < nq) tile[rr * BP_LP + lane] = v[x];
+                }
+            }
         }
         __syncthreads();
         const float scf = (float)s.scale;
