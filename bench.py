@@ -71,7 +71,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="tvs2000")
-    ap.add_argument("--flags", type=int, default=0, help="TVS_FLAG_* bits (0 = default float path)")
+    ap.add_argument("--flags", type=int, default=0, help="TVS_FLAG_* bits (0: double elevations, reciprocal-product slope, early exit)")
     ap.add_argument("--cpu-window", type=int, default=128, help="side of the centre window the oracle times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-summary", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.md"))
@@ -376,16 +376,25 @@ def bench_serve(args):
         srv.close()
         return res, wall, st
 
-    log("paced stream ...")
-    res, wall, st = run_server(True)
-    lat = np.array([r.latency_ms for r in res])
-    lat_s = np.array([r.latency_ms for r, q in zip(res, reqs) if q[1] == "s"])
-    lat_t = np.array([r.latency_ms for r, q in zip(res, reqs) if q[1] == "t"])
-    assert all(r.status == 0 for r in res)
-    log(f"paced: p50 {np.percentile(lat, 50):.2f} ms p99 {np.percentile(lat, 99):.2f} ms over {wall:.1f} s")
+    def pct(res, kind=None):
+        v = np.array([r.latency_ms for r, q in zip(res, reqs) if kind is None or q[1] == kind])
+        return (float(np.percentile(v, 50)), float(np.percentile(v, 99))) if len(v) else (None, None)
+
+    # The first server of a process grows the device memory pool and the pinned staging while it
+    # serves; the headline pass runs after a flood pass has done that, the cold pass is reported.
+    log("paced stream, cold process ...")
+    res_c, _, st_c = run_server(True)
+    assert all(r.status == 0 for r in res_c)
+    log(f"cold: p99 {pct(res_c)[1]:.2f} ms, singular p99 {pct(res_c, 's')[1]:.2f} ms")
     log("flood (every request queued at once) ...")
     res_f, wall_f, st_f = run_server(False)
+    assert all(r.status == 0 for r in res_f)
     log(f"flood: {len(reqs) / wall_f:.1f} req/s")
+    log("paced stream ...")
+    res, wall, st = run_server(True)
+    assert all(r.status == 0 for r in res)
+    log(f"paced: p50 {pct(res)[0]:.2f} ms p99 {pct(res)[1]:.2f} ms, singular p99 {pct(res, 's')[1]:.2f} ms "
+        f"over {wall:.1f} s")
     log("plain path, one request at a time ...")
     dg = [torch.from_numpy(g).cuda() for g in grids]
     tvs.singular_viewshed(dg[0], dx, h0, n, R[0], 0, 0)
@@ -401,17 +410,17 @@ def bench_serve(args):
     log(f"plain: {len(reqs) / plain:.1f} req/s")
     line = {
         "metric": "p50/p99 serve latency (ms), Poisson request stream",
-        "value": float(np.percentile(lat, 99)),
+        "value": pct(res)[1],
         "unit": "ms (p99)",
         "n_gpus": 1, "steps": 1, "warmup": 1, "ms_per_step": wall * 1e3,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": f"{len(reqs)} requests, Poisson {args.serve_rate:g}/s for {args.serve_seconds:g} s: "
                                "80% singular on grids 512..4096, 20% total on grids 256..1024, 10 m, observer 1.5 m, "
                                "180 sectors, max distance = grid extent", "requests": len(reqs)},
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
-                       "singular_p50": float(np.percentile(lat_s, 50)), "singular_p99": float(np.percentile(lat_s, 99)),
-                       "total_p50": float(np.percentile(lat_t, 50)) if len(lat_t) else None,
-                       "total_p99": float(np.percentile(lat_t, 99)) if len(lat_t) else None},
+        "latency_ms": {"p50": pct(res)[0], "p99": pct(res)[1], "singular_p50": pct(res, "s")[0],
+                       "singular_p99": pct(res, "s")[1], "total_p50": pct(res, "t")[0], "total_p99": pct(res, "t")[1]},
+        "latency_ms_cold_process": {"p50": pct(res_c)[0], "p99": pct(res_c)[1], "singular_p99": pct(res_c, "s")[1],
+                                    "total_p99": pct(res_c, "t")[1]},
         "served_req_per_s": len(reqs) / wall,
         "capacity_req_per_s": len(reqs) / wall_f,
         "plain_one_at_a_time_req_per_s": len(reqs) / plain,
