@@ -187,6 +187,8 @@ def main():
         "relocate_alg_GBps": (reloc_bytes / (reloc_ms / 1e3) / 1e9) if reloc_ms > 0 else None,
         "relocate_frac_hbm": ((reloc_bytes / (reloc_ms / 1e3) / 1e9) / HBM_PEAK_GBS) if reloc_ms > 0 else None,
         "evals_per_s_sweep_only": evals * args.steps / (sweep_ms / 1e3) if sweep_ms > 0 else None,
+        "chunks_per_step": st.chunks,
+        "scratch_bytes": st.scratch_bytes,
     }
 
     cpu = None

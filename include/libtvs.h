@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 6
+#define TVS_ABI_VERSION 7
 
 enum tvs_status {
     TVS_OK = 0,
@@ -82,6 +82,12 @@ enum tvs_status {
 #define TVS_FLAG_AUTOTUNE 0x80u   /* batches only: time the candidate launch shapes on a sample of
                                      the batch before building it and keep the fastest for batches
                                      of the same size class (process-wide) */
+#define TVS_FLAG_COMPACT 0x100u   /* total viewshed and batches: compacted skewed buffers (Section 3.1,
+                                     the second compaction of Figure 4): skewed row t of a base frame
+                                     with Hx rows is stored in row t mod (Hx + 1), since rows that far
+                                     apart hold disjoint column ranges. A sector then takes Hx + 1
+                                     rows instead of Hx + d_max + 1, so a chunk holds more sectors
+                                     within the same scratch budget. Same results bit for bit. */
 
 /* Per-call measurement filled by the _ex entry points when `stats` is non-NULL. Kernel
  * times come from HIP events recorded around each launch on the call's stream; asking for

@@ -72,7 +72,17 @@ Sector plan_sector(int k, int n, int H, int W, double dx, double R) {
     col_offset(s.T, s.Wx - 1, dmax, rmax);
     s.t0 = -dmax - 1;
     s.nrows = s.Hx - s.t0;
+    s.wrap = 0;
+    s.prows = s.nrows;
     return s;
+}
+
+// Skewed row t holds the samples of the columns with -1 < t + y_j < Hx (Section 3.1, Algorithm 6),
+// row t + Hx + 1 those with -1 - t - Hx - 1 < y_j < -1 - t: disjoint column ranges. Rows congruent
+// modulo Hx + 1 therefore share one stored row, and the rows t0 .. Hx - 1 fit Hx + 1 rows.
+void compact_layout(Sector &s) {
+    s.wrap = s.Hx + 1;
+    s.prows = std::min(s.nrows, s.wrap);
 }
 
 // Elevations and the observer height must be finite, and either 0 or at least 2^-60 m in
@@ -103,7 +113,8 @@ int check_host_dem(const float *dem, int rows, int cols) {
 
 int check_flags(uint32_t flags, bool accumulation) {
     const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_NO_PRUNE |
-                           TVS_FLAG_SLOPE_F32 | (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS : 0u);
+                           TVS_FLAG_SLOPE_F32 |
+                           (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS | TVS_FLAG_COMPACT : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
     if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
         return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
@@ -177,7 +188,7 @@ std::vector<Chunk> make_chunks(const std::vector<Sector> &S, size_t elem, int pi
     while (k < n) {
         Chunk c{k, k, 0, 0, 0};
         while (c.k1 < n && c.k1 - c.k0 < TVS_CHUNK) {
-            const size_t b = (size_t)S[c.k1].nrows * pitch * (elem + sizeof(uint32_t));
+            const size_t b = (size_t)S[c.k1].prows * pitch * (elem + sizeof(uint32_t));
             if (c.k1 > c.k0 && c.bytes + b > budget) break;
             c.bytes += b;
             c.maxRows = std::max(c.maxRows, S[c.k1].nrows);
@@ -212,7 +223,9 @@ ChunkArgs chunk_args(const std::vector<Sector> &S, const Chunk &c, int H, int W,
         d.K = s.K;
         d.t0 = s.t0;
         d.nrows = s.nrows;
-        off += (int64_t)s.nrows * pitch;
+        d.wrap = s.wrap;
+        d.winv = s.wrap ? 1.0f / (float)s.wrap : 0.0f;
+        off += (int64_t)s.prows * pitch;
     }
     return a;
 }
@@ -272,9 +285,12 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
                     f64 ? "; TVS_FLAG_SLOPE_F32 takes float rows" : "");
 
     std::vector<Sector> S;
-    if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));
+    if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));  // plain rows, copied out
     else
-        for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+        for (int k = 0; k < n; ++k) {
+            S.push_back(plan_sector(k, n, H, W, dx, R));
+            if (flags & TVS_FLAG_COMPACT) compact_layout(S.back());
+        }
     const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, budget ? budget : scratch_budget());
     size_t maxChunk = 0;
     for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
@@ -521,7 +537,10 @@ size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t fl
     const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
     std::vector<Sector> S;
-    for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, H, W, dx, R));
+    for (int k = 0; k < n; ++k) {
+        S.push_back(plan_sector(k, n, H, W, dx, R));
+        if (flags & TVS_FLAG_COMPACT) compact_layout(S.back());
+    }
     size_t maxChunk = 0;
     for (const Chunk &c : make_chunks(S, elem, pitch_of(H, W), budget ? budget : scratch_budget()))
         maxChunk = std::max(maxChunk, c.bytes);

@@ -138,7 +138,7 @@ int check_tiles(const tvs_tile *tiles, int ntiles, int n) {
 
 int check_batch_flags(uint32_t flags) {
     const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F32 | TVS_FLAG_COUNT_EVALS |
-                           TVS_FLAG_AUTOTUNE;
+                           TVS_FLAG_AUTOTUNE | TVS_FLAG_COMPACT;
     if (flags & ~known)
         return fail(TVS_EINVAL, "unsupported flags 0x%x for a batch (the batched sweep always uses the early exit)",
                     flags);
@@ -158,7 +158,7 @@ int plan_chunks(tvs_batch *b, size_t budget) {
         c.k0 = c.k1 = k;
         while (c.k1 < b->n && (int64_t)b->ntiles * (c.k1 - c.k0 + 1) < 65536) {
             size_t add = 0;
-            for (int t = 0; t < b->ntiles; ++t) add += (size_t)b->sectors[t][c.k1].nrows * pitch[t] * 4;
+            for (int t = 0; t < b->ntiles; ++t) add += (size_t)b->sectors[t][c.k1].prows * pitch[t] * 4;
             if (c.k1 > c.k0 && c.vbytes + add > budget) break;
             c.vbytes += add;
             ++c.k1;
@@ -201,6 +201,8 @@ void build_tables(tvs_batch *b, std::vector<BatchEnt> &ent, std::vector<BatchTil
                 e.s.K = s.K;
                 e.s.t0 = s.t0;
                 e.s.nrows = s.nrows;
+                e.s.wrap = s.wrap;
+                e.s.winv = s.wrap ? 1.0f / (float)s.wrap : 0.0f;
                 e.dem = T.d_dem;
                 e.H = T.rows;
                 e.W = T.cols;
@@ -208,7 +210,7 @@ void build_tables(tvs_batch *b, std::vector<BatchEnt> &ent, std::vector<BatchTil
                 e.h0 = T.obs_height;
                 e.h0f = (float)T.obs_height;
                 ent.push_back(e);
-                off += (int64_t)s.nrows * pitch;
+                off += (int64_t)s.prows * pitch;
             }
             BatchTile q;
             memset(&q, 0, sizeof(q));
@@ -325,7 +327,10 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
         const tvs_tile &T = tiles[t];
         std::vector<Sector> S;
         S.reserve(n);
-        for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist));
+        for (int k = 0; k < n; ++k) {
+            S.push_back(plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist));
+            if (flags & TVS_FLAG_COMPACT) compact_layout(S.back());
+        }
         for (const Sector &s : S) b->maxK = std::max(b->maxK, std::min(s.K, std::max(s.Hx, s.Wx)));
         b->sectors.push_back(std::move(S));
         b->maxWx = std::max(b->maxWx, std::max(T.rows, T.cols));

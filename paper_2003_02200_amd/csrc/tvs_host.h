@@ -33,7 +33,12 @@ struct Sector {
     double scale;  // (pi / 2n) spacing^2 / cos^2 s'
     double clip;   // rho^2 - K^2
     int t0, nrows;
+    int wrap;      // 0: plain layout; Hx + 1: compacted layout (skewed row t in row t mod wrap)
+    int prows;     // rows the sector's skewed buffers take: nrows, or Hx + 1 compacted
 };
+
+// Switches the sector to the compacted layout of its skewed buffers.
+void compact_layout(Sector &s);
 
 // Elevations and the observer height must be finite, and either 0 or at least 2^-60 m in
 // magnitude. The second rule keeps every quantity of the sweep a multiple of 2^-83, so no slope

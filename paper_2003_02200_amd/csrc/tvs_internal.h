@@ -25,6 +25,9 @@ struct SecDev {
     int32_t K;      // last target index in range, TVS_K_UNBOUNDED if max_dist never binds
     int32_t t0;     // first skewed row
     int32_t nrows;  // skewed rows t0 .. t0 + nrows - 1 (the last is Hx - 1)
+    int32_t wrap;   // 0: row t is stored at row t - t0 of the sector's block; else (compacted
+                    // layout, wrap = Hx + 1) at row t mod wrap
+    float winv;     // 1 / wrap rounded to float (a first guess of the quotient)
 };
 
 struct ChunkArgs {

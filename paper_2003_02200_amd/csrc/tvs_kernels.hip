@@ -156,6 +156,21 @@ __device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v) {
     return v;
 }
 
+// Stored row of skewed row t of sector s: t - t0, or in the compacted layout t mod wrap (the
+// float quotient is off by at most one, corrected by one step).
+__device__ __forceinline__ int skw_prow(const SecDev &s, int t) {
+    if (!s.wrap) return t - s.t0;
+    int p = t - s.wrap * (int)floorf((float)t * s.winv);
+    if (p < 0) p += s.wrap;
+    else if (p >= s.wrap) p -= s.wrap;
+    return p;
+}
+
+// Element offset of skewed row t of sector s in its skewed buffers.
+__device__ __forceinline__ int64_t skw_row(const SecDev &s, int t, int pitch) {
+    return s.off + (int64_t)skw_prow(s, t) * pitch;
+}
+
 // ------------------------------------------------------------------------ small kernels
 
 // Entry i holds {m, RN(1/m)} for m = i + 1, so that the 32-step blocks of the sweep, which
@@ -293,9 +308,16 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
         float v[8];
         const bool more = b + 1 < nb;
         if (more) reloc_load(f, uA + RL_RING + b * RL_TB, wv, lane, v);
+        // stored row of this thread's first skewed row of the batch; the others follow 4 apart
+        const int pf = skw_prow(s, tb + wv);
 #pragma unroll
         for (int i = 0; i < 8; ++i) {
             const int t = tb + wv + 4 * i;
+            int p = pf + 4 * i;
+            if (s.wrap) {
+                if (s.wrap > 28) p -= p >= s.wrap ? s.wrap : 0;
+                else p = skw_prow(s, t);
+            }
             if (mine && t <= tE && t >= tfirst && t <= tlast) {
                 const int u = t + d;
                 const float av = ring[(u & (RL_RING - 1)) * RL_LP + lane];
@@ -306,7 +328,7 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
                 }
                 // + 0 turns a -0 elevation into +0 (no other value changes): the sweep's sign
                 // tests rely on slopes never being -0
-                skw[s.off + (int64_t)(t - s.t0) * a.pitch + q] = add_rn((Tz)z, (Tz)0);
+                skw[s.off + (int64_t)p * a.pitch + q] = add_rn((Tz)z, (Tz)0);
             }
         }
         if (more) {
@@ -451,7 +473,7 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
     const int jhi = row_last(s.T, t, Hx, Wx);
     const int nt = jhi - jlo + 1;
     if (nt <= 0) return 0;
-    const Tz *src = skw + s.off + (int64_t)ri * a.pitch + jlo;
+    const Tz *src = skw + skw_row(s, t, a.pitch) + jlo;
     for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
         const int q = x - TVS_SWEEP_PAD;
         row[x] = (q >= 0 && q < nt) ? src[q] : neg_inf<Tz>();
@@ -522,7 +544,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
     if (nt == 0) return;
     if (work && threadIdx.x == 0) wg_work = 0;
     const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE>(row, nt, s.K, h0_of<Tz>(a), tab,
-                                                         V + s.off + (int64_t)ri * a.pitch + jlo, work != nullptr);
+                                                         V + skw_row(s, s.t0 + ri, a.pitch) + jlo,
+                                                         work != nullptr);
     if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
@@ -596,7 +619,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         const int nt = gather_row<Tz>(E.dem, E.H, E.W, E.s, ri, row, jlo);
         if (nt > 0)
             evals += sweep_row<Tz, NW, RCP, true>(row, nt, E.s.K, h0_of<Tz>(E), tab,
-                                                  V + E.s.off + (int64_t)ri * E.pitch + jlo, work != nullptr);
+                                                  V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
+                                                  work != nullptr);
         __syncthreads();  // the row is read by every wavefront before the next gather
     }
     if (work) add_work(work, wg_work, evals, blockIdx.x);
@@ -621,7 +645,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
     const int wv = threadIdx.x >> 6;
     const int K = s.K;
     const Tz h0 = h0_of<Tz>(a);
-    uint32_t *dst = V + s.off + (int64_t)ri * a.pitch + jlo;
+    uint32_t *dst = V + skw_row(s, s.t0 + ri, a.pitch) + jlo;
     unsigned long long evals = 0;
     for (int q = wv; q < nt; q += NW) {
         const Tz *zp = row + TVS_SWEEP_PAD + q;
@@ -683,6 +707,7 @@ __device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W
     __shared__ uint32_t tile[BP_MAXR * BP_LP];
     __shared__ int col_d[BP_T];
     __shared__ double col_r[BP_T];
+    __shared__ int row_p[BP_MAXR];  // compacted layout: stored row of each staged skewed row
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int j = j0 + lane;
@@ -714,6 +739,8 @@ __device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W
             s.K = g.K;
             s.t0 = __builtin_amdgcn_readfirstlane(g.t0);
             s.nrows = g.nrows;
+            s.wrap = __builtin_amdgcn_readfirstlane(g.wrap);
+            s.winv = g.winv;
         }
         // the block's base-frame rectangle [plo, phi] x [qlo, qhi]
         int plo, phi, qlo, qhi;
@@ -738,17 +765,22 @@ __device__ __forceinline__ void backproj_block(SecFn sec, int nsec, int H, int W
             col_d[threadIdx.x] = d;
             col_r[threadIdx.x] = r;
         }
+        if (s.wrap) {
+            for (int x = threadIdx.x; x < nr; x += blockDim.x) row_p[x] = skw_prow(s, s.t0 + rbase + x);
+            __syncthreads();
+        }
         {
             // rows are staged in rounds of 12 per wavefront, each round's loads all in flight
             // before its LDS stores
             constexpr int RND = 12;
-            const uint32_t *src = V + s.off + (int64_t)rbase * pitch + qlo + min(lane, nq - 1);
+            const uint32_t *src = V + s.off + qlo + min(lane, nq - 1);
             for (int r0 = wv; r0 < nr; r0 += 4 * RND) {
                 uint32_t v[RND];
 #pragma unroll
                 for (int x = 0; x < RND; ++x) {
                     const int rr = r0 + 4 * x;
-                    if (rr < nr) v[x] = src[(int64_t)rr * pitch];
+                    const int p = s.wrap ? row_p[min(rr, nr - 1)] : rbase + rr;
+                    if (rr < nr) v[x] = src[(int64_t)p * pitch];
                 }
 #pragma unroll
                 for (int x = 0; x < RND; ++x) {
@@ -1140,7 +1172,6 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st) {
     const size_t lds = sweep_lds_bytes(maxWx, f64);
-    hipError_t e = hipSuccess;
 #define TVS_BATCH_GO(TZ, NW, RCP, TAB)                                                                  \
     do {                                                                                                \
         auto f = k_sweep_batch<TZ, NW, RCP>;                                                            \

@@ -61,7 +61,7 @@ def test_rejects_bad_flag_combinations(tvs):
     d = np.zeros(4, np.float32)
     out = np.zeros(4, np.float64)
     vp = C.c_void_p
-    for flags in (0x80, 0x100, 0x80000000, 0x41):  # 0x41: float and double decisions together
+    for flags in (0x80, 0x200, 0x80000000, 0x41):  # 0x41: float and double decisions together
         rc = L.tvs_total_viewshed_ex(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp),
                                      flags, None, None)
         assert rc == -1, flags
@@ -135,7 +135,7 @@ def test_batch_rejects_bad_arguments(tvs):
     t[1] = tvs.Tile(None, 32, 4, 4, 10.0, 1.5, 100.0)
     assert L.tvs_batch_create(t, 2, 8, 0, C.byref(h)) == -1
     t[1] = tvs.Tile(16, 32, 4, 4, 10.0, 1.5, 100.0)
-    for flags in (tvs.FLAG_SWEEP_SCAN, tvs.FLAG_ACC_KAHAN32, tvs.FLAG_NO_PRUNE, 0x41, 0x100):
+    for flags in (tvs.FLAG_SWEEP_SCAN, tvs.FLAG_ACC_KAHAN32, tvs.FLAG_NO_PRUNE, 0x41, 0x200):
         assert L.tvs_batch_create(t, 2, 8, flags, C.byref(h)) == -1, flags
     assert L.tvs_batch_create(t, 2, 0, 0, C.byref(h)) == -1
     assert L.tvs_batch_create(t, 0, 8, 0, C.byref(h)) == -1

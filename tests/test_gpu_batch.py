@@ -116,6 +116,33 @@ def test_batch_counts_and_chunking(tvs, monkeypatch):
     b.close()
 
 
+def test_batch_compact_layout(tvs, monkeypatch):
+    """Batches with compacted skewed buffers (TVS_FLAG_COMPACT) give the plain batch's maps bit
+    for bit, with one chunk and with many."""
+    import torch
+
+    n = 30
+    host, dems = _make(TILES, seed=9)
+    outs_p = _outs(TILES, 0.0)
+    outs_c = _outs(TILES, 0.0)
+    tl_p = [(dems[x], outs_p[x], *TILES[x][2:]) for x in range(len(TILES))]
+    tl_c = [(dems[x], outs_c[x], *TILES[x][2:]) for x in range(len(TILES))]
+    for budget in (None, "1"):
+        if budget:
+            monkeypatch.setenv("TVS_SCRATCH_MB", budget)
+        note(f"batch compact budget={budget}")
+        bp = tvs.Batch(tl_p, n)
+        bc = tvs.Batch(tl_c, n, flags=tvs.FLAG_COMPACT)
+        bp.run()
+        bc.run()
+        torch.cuda.synchronize()
+        assert bc.info().chunks <= bp.info().chunks
+        for x in range(len(TILES)):
+            assert torch.equal(outs_p[x], outs_c[x]), f"tile {x}"
+        bp.close()
+        bc.close()
+
+
 def test_batch_autotune(tvs):
     import torch
 

@@ -240,6 +240,39 @@ def test_total_small(tvs, orc, H, W, n, R, kind):
         np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, R, prec=prec), rtol=1e-12, atol=0)
 
 
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES)
+def test_total_compact_layout(tvs, orc, H, W, n, R, kind):
+    """The compacted skewed layout (TVS_FLAG_COMPACT: skewed row t in row t mod (Hx + 1)) moves
+    rows, not results: maps bit-identical to the plain layout in the default and float modes and
+    for the lane-per-target sweep, equal to the oracle, in no more scratch. The wide and tall
+    shapes wrap the rows many times over."""
+    dem = _dem(H, W, kind, seed=13)
+    plain0 = None
+    for flags, prec in (MODES[0], MODES[2]):
+        note(f"compact H={H} W={W} n={n} R={R} kind={kind} flags={flags}")
+        plain, st_p = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=flags, stats=True)
+        comp, st_c = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=flags | tvs.FLAG_COMPACT, stats=True)
+        assert np.array_equal(plain, comp), f"flags={flags}"
+        assert st_c.scratch_bytes <= st_p.scratch_bytes and st_c.chunks <= st_p.chunks
+        np.testing.assert_allclose(comp, orc.total(dem, 10.0, 1.5, n, R, prec=prec), rtol=1e-12, atol=0)
+        plain0 = plain if plain0 is None else plain0
+    scan = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SWEEP_SCAN | tvs.FLAG_COMPACT)
+    assert np.array_equal(scan, plain0)
+
+
+def test_compact_layout_many_chunks(tvs, monkeypatch):
+    """A 1 MB scratch budget splits the sectors into many chunks; the compacted layout fits more
+    sectors in each and the map stays bit-identical."""
+    dem = _dem(130, 70, "fractal", seed=17)
+    ref = tvs.total_viewshed(dem, 10.0, 1.5, 180, 700.0)
+    monkeypatch.setenv("TVS_SCRATCH_MB", "1")
+    note("compact 130x70 n=180 with a 1 MB scratch budget")
+    plain, st_p = tvs.total_viewshed(dem, 10.0, 1.5, 180, 700.0, stats=True)
+    comp, st_c = tvs.total_viewshed(dem, 10.0, 1.5, 180, 700.0, flags=tvs.FLAG_COMPACT, stats=True)
+    assert st_p.chunks > 10 and st_c.chunks < st_p.chunks
+    assert np.array_equal(plain, ref) and np.array_equal(comp, ref)
+
+
 def test_flat_full_disc_on_gpu(tvs):
     """P1 through the GPU: interior cells of flat ground get pi R^2."""
     H = W = 90
