@@ -39,7 +39,8 @@ struct ChunkArgs {
     float h0f;      // observer height rounded to float
     int32_t k_base; // global index of s[0]
     int32_t pov_i, pov_j;  // singular POV (grid cell)
-    int32_t pad0, pad1;
+    int32_t rmq;    // sweep: 1 when the early exit's range-maximum table is in LDS (set by launch_sweep)
+    int32_t pad1;
 };
 
 // One (tile, sector) of a batch chunk: the sector's geometry (off = element offset of its skewed
@@ -121,6 +122,8 @@ struct MaskArgs {
     uint32_t *count;        // nullable: POVs that see the cell
 };
 hipError_t launch_mask_multi(const MaskArgs &a, hipStream_t st);
+// LDS of a sweep workgroup for rows of up to maxWx samples, without the early exit's
+// range-maximum table (the launches add it when it fits).
 size_t sweep_lds_bytes(int maxWx, bool f64);
 constexpr int BATCH_BLOCK = 64;  // cells per side of a back-projection block
 

@@ -27,6 +27,8 @@
 // reciprocal, one product and one FMA correction, exact for every integer m in range).
 // Explicit _rn intrinsics keep the compiler from contracting any step into an FMA.
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <math.h>
 #include <stdint.h>
 
@@ -66,21 +68,23 @@ __device__ __forceinline__ double sub_rn(double a, double b) { return __dsub_rn(
 // compare writes VCC and the add-with-carry takes it as carry-in (two VALU instructions; the
 // compiler does not form this pair from C++). max equals "vis ? th : mx" here: slopes are
 // never NaN except on sentinel lanes, where both keep mx.
+// The maximum is taken in the same block: slopes are never NaN, so no canonicalising of the
+// running maximum is needed between blocks.
 __device__ __forceinline__ void vis_step(float th, float &mx, uint32_t &bits) {
-    asm("v_cmp_gt_f32 vcc, %1, %2\n\t"
-        "v_addc_co_u32 %0, vcc, %0, %0, vcc"
-        : "+v"(bits)
-        : "v"(th), "v"(mx)
+    asm("v_cmp_gt_f32 vcc, %2, %1\n\t"
+        "v_addc_co_u32 %0, vcc, %0, %0, vcc\n\t"
+        "v_max_f32 %1, %1, %2"
+        : "+v"(bits), "+v"(mx)
+        : "v"(th)
         : "vcc");
-    mx = __builtin_fmaxf(mx, th);
 }
 __device__ __forceinline__ void vis_step(double th, double &mx, uint32_t &bits) {
-    asm("v_cmp_gt_f64 vcc, %1, %2\n\t"
-        "v_addc_co_u32 %0, vcc, %0, %0, vcc"
-        : "+v"(bits)
-        : "v"(th), "v"(mx)
+    asm("v_cmp_gt_f64 vcc, %2, %1\n\t"
+        "v_addc_co_u32 %0, vcc, %0, %0, vcc\n\t"
+        "v_max_f64 %1, %1, %2"
+        : "+v"(bits), "+v"(mx)
+        : "v"(th)
         : "vcc");
-    mx = __builtin_fmax(mx, th);
 }
 
 template <typename Tz> struct Tab;
@@ -341,13 +345,17 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
 
 // -------------------------------------------------------------------------------- sweep
 
+// Levels of the early exit's range-maximum table: windows of 1, 2, .., 32 blocks of 32 samples,
+// answering the maximum over any 1..64 consecutive blocks with two reads.
+constexpr int RMQ_LEVELS = 6;
+
 // Ring sums of 32 visibility bits: step m0+s lands in bit 31-s, so the ring weight 2m+1 of set
 // bit b is (2 m0 + 63) - 2b, and sum_b b = sum_k 2^k popc(bits & M_k).
 struct RingAcc {
     uint32_t base = 0;                                // sum over blocks of (2 m0 + 63) popc(bits)
     uint32_t q0 = 0, q1 = 0, q2 = 0, q3 = 0, q4 = 0;  // sum over blocks of popc(bits & M_k)
     __device__ __forceinline__ void add(uint32_t bits, int m0) {
-        base += (uint32_t)(2 * m0 + 63) * (uint32_t)__popc(bits);
+        base += __umul24((uint32_t)(2 * m0 + 63), (uint32_t)__popc(bits));
         q0 += __popc(bits & 0xAAAAAAAAu);
         q1 += __popc(bits & 0xCCCCCCCCu);
         q2 += __popc(bits & 0xF0F0F0F0u);
@@ -377,19 +385,35 @@ struct RingAcc {
 template <typename Tz, int DIR, bool RCP, bool PRUNE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
-                                              const Tz *bnd, int pbase, bool live, int &done) {
+                                              const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
+                                              bool live, int &done) {
     // a lane past the row end starts with a +inf horizon: it never sees a target and never
     // holds back the early exit (its sums are discarded)
     Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
     const int mfull = (mb == K) ? K - 1 : mb;
     auto hidden_from = [&](int mm) -> bool {
-        const Tz zs = bnd[(pbase + DIR * mm) >> 5];
+        // blocks a lane may still read: from the nearest at step mm to bfar, the farthest any
+        // lane of the wavefront reaches within K (the range table), else to the row end
+        const int bnear = (pbase + DIR * mm) >> 5;
+        const int lo = DIR > 0 ? bnear : bfar, hi = DIR > 0 ? bfar : bnear;
+        const int len = hi - lo + 1;
+        Tz zs;
+        if (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) {
+            const int l = min(31 - __builtin_clz(len), RMQ_LEVELS - 1);
+            const float *T = rmq + l * nb;
+            float zf;  // the table holds no NaN: a plain max, without canonicalising its inputs
+            asm("v_max_f32 %0, %1, %2" : "=v"(zf) : "v"(T[lo]), "v"(T[hi - (1 << l) + 1]));
+            zs = (Tz)zf;
+        } else {
+            zs = bnd[bnear];
+        }
         const Tz b = vmax(slope<RCP>(sub_rn(zs, h), tab[mm - 1]), (Tz)0);
         // every lane of the (fully active) wavefront agrees; a wave-uniform answer keeps the
         // step counter, and with it the table loads, scalar
         return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
     };
     RingAcc ra;
+    uint32_t bits = 0;
     int m = 1;
     bool stop = false;
     for (; m + 31 <= mfull; m += 32) {
@@ -399,10 +423,11 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
             break;
         }
         const auto *t = static_cast<const typename Tab<Tz>::type *>(__builtin_assume_aligned(tab + (m - 1), 256));
-        uint32_t bits = 0;
 #pragma unroll
         for (int s = 0; s < 32; ++s) vis_step(slope<RCP>(sub_rn(zp[DIR * (m + s)], h), t[s]), mx, bits);
-        ra.add(bits, m);
+        // 32 steps have shifted every earlier bit out: `bits` is this block's. Far from the POVs
+        // most blocks see nothing on any lane, and skip the ring sums.
+        if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
     }
     if (PRUNE && !stop && m > 1 && m <= mb) stop = hidden_from(m);
     uint32_t acc = ra.total();
@@ -420,19 +445,38 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     return e;
 }
 
+// x rounded up to float: an upper bound of x that the table can hold in half the bytes.
+__device__ __forceinline__ float ru_float(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = __int_as_float(__float_as_int(f) + (f >= 0.0f ? 1 : -1));
+    return f;
+}
+__device__ __forceinline__ float ru_float(float x) { return x; }
+
 // Per-block elevation maxima of a row of nt samples (followed by -inf sentinels): pre[b] is the
 // maximum over blocks 0..b, suf[b] over blocks b..nb-1, each scanned by one wavefront with the
-// wavefront prefix-max.
+// wavefront prefix-max. With `rmq`, level l of the table holds at rmq[l nb + b] the maximum over
+// blocks b .. min(b + 2^l, nb) - 1, rounded up to float.
 template <typename Tz>
-__device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre) {
+__device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq) {
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         Tz m = z[32 * b];
 #pragma unroll
         for (int i = 1; i < 32; ++i) m = vmax(m, z[32 * b + i]);
         suf[b] = m;
         pre[b] = m;
+        if (rmq) rmq[b] = ru_float(m);
     }
     __syncthreads();
+    if (rmq) {
+        for (int l = 1; l < RMQ_LEVELS; ++l) {
+            const float *src = rmq + (l - 1) * nb;
+            float *dst = rmq + l * nb;
+            const int half = 1 << (l - 1);
+            for (int b = threadIdx.x; b < nb; b += blockDim.x) dst[b] = fmaxf(src[b], src[min(b + half, nb - 1)]);
+            __syncthreads();
+        }
+    }
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (wv < 2) {
@@ -488,11 +532,13 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
 template <typename Tz, int NW, bool RCP, bool PRUNE>
 __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                               const typename Tab<Tz>::type *__restrict__ tab,
-                                              uint32_t *__restrict__ dst, bool count) {
+                                              uint32_t *__restrict__ dst, bool count, bool use_rmq) {
     const int nb = (nt + 31) >> 5;
     Tz *suf = row + nt + 2 * TVS_SWEEP_PAD;
     Tz *pre = suf + nb;
-    if (PRUNE) block_bounds(row + TVS_SWEEP_PAD, nb, suf, pre);
+    float *rmq = use_rmq ? reinterpret_cast<float *>(pre + nb) : nullptr;
+    if (PRUNE) block_bounds(row + TVS_SWEEP_PAD, nb, suf, pre, rmq);
+    const int Kc = min(K, nt);  // K may be unbounded
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nseg = (nt + 63) >> 6;
@@ -509,8 +555,9 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         const int fwd = min(K, nt - 1 - q0);
         const int bwd = min(K, top);
         int df, db;
-        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, q0, live, df);
-        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, top, live, db);
+        const int bfar_f = min(nb - 1, (q0 + 63 + Kc) >> 5), bfar_b = max(0, q0 - Kc) >> 5;
+        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, live, df);
+        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, live, db);
         if (live) dst[q] = U | (e << 30);
         if (count && live) evals += (uint32_t)(min(df, min(K, nt - 1 - q)) + min(db, min(K, q)));
     }
@@ -545,7 +592,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
     if (work && threadIdx.x == 0) wg_work = 0;
     const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE>(row, nt, s.K, h0_of<Tz>(a), tab,
                                                          V + skw_row(s, s.t0 + ri, a.pitch) + jlo,
-                                                         work != nullptr);
+                                                         work != nullptr, a.rmq != 0);
     if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
@@ -599,7 +646,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
                                                          const uint32_t *__restrict__ items, int nitems,
                                                          unsigned int *__restrict__ counter, uint32_t *__restrict__ V,
                                                          const typename Tab<Tz>::type *__restrict__ tab,
-                                                         unsigned long long *__restrict__ work) {
+                                                         unsigned long long *__restrict__ work, int rmq) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Tz *row = reinterpret_cast<Tz *>(lds_raw);
     __shared__ int next;
@@ -620,7 +667,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         if (nt > 0)
             evals += sweep_row<Tz, NW, RCP, true>(row, nt, E.s.K, h0_of<Tz>(E), tab,
                                                   V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
-                                                  work != nullptr);
+                                                  work != nullptr, rmq != 0);
         __syncthreads();  // the row is read by every wavefront before the next gather
     }
     if (work) add_work(work, wg_work, evals, blockIdx.x);
@@ -1073,6 +1120,23 @@ size_t sweep_lds_bytes(int maxWx, bool f64) {
     return (size_t)(maxWx + 2 * TVS_SWEEP_PAD + 2 * ((maxWx + 31) / 32)) * (f64 ? sizeof(double) : sizeof(float));
 }
 
+// The sweep's LDS with the early exit's range-maximum table when it fits the workgroup limit
+// (rmq = 1), else without it (rmq = 0).
+static size_t sweep_lds_launch(int maxWx, bool f64, int &rmq) {
+    const size_t base = sweep_lds_bytes(maxWx, f64);
+    const size_t full = base + (size_t)RMQ_LEVELS * ((maxWx + 31) / 32) * sizeof(float);
+    // the device's limit, queried once per device (the first launch on it is not captured)
+    static std::atomic<int> caps[64];
+    int dev = 0, cap = 0;
+    if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+        cap = caps[dev].load();
+        if (cap == 0 && hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
+            caps[dev].store(cap);
+    }
+    rmq = full + 64 <= (size_t)cap ? 1 : 0;  // + the kernels' static LDS
+    return rmq ? full : base;
+}
+
 hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st) {
     k_divtab<<<(n + 255) / 256, 256, 0, st>>>(tab32, tab64, n);
     return hipGetLastError();
@@ -1141,11 +1205,12 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
                         const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
                         unsigned long long *work, hipStream_t st) {
     const dim3 grid(maxRows, a.nsec);
-    const size_t lds = sweep_lds_bytes(maxWx, f64);
+    ChunkArgs b = a;
+    const size_t lds = sweep_lds_launch(maxWx, f64, b.rmq);
     switch (sweep_waves(lds)) {
-    case 4: return sweep_nw<4>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
-    case 8: return sweep_nw<8>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
-    default: return sweep_nw<16>(a, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    case 4: return sweep_nw<4>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    case 8: return sweep_nw<8>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    default: return sweep_nw<16>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
     }
 }
 
@@ -1171,12 +1236,13 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
 hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st) {
-    const size_t lds = sweep_lds_bytes(maxWx, f64);
+    int rmq = 0;
+    const size_t lds = sweep_lds_launch(maxWx, f64, rmq);
 #define TVS_BATCH_GO(TZ, NW, RCP, TAB)                                                                  \
     do {                                                                                                \
         auto f = k_sweep_batch<TZ, NW, RCP>;                                                            \
         if (grid == 0) return set_lds(f, lds);                                                          \
-        f<<<grid, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work);                       \
+        f<<<grid, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work, rmq);                  \
     } while (0)
     switch (waves) {
     case 2:
