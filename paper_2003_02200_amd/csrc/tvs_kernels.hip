@@ -375,9 +375,12 @@ struct RingAcc {
 // the bit mask, max. Returns in `done` the number of steps taken.
 //
 // Early exit (PRUNE): before each block the wavefront stops when no target from step m on can
-// be visible on any live lane. `bnd` holds maxima of the row's elevations per 32-sample block,
-// accumulated away from the POVs (suffix maxima forward, prefix maxima backward), so
-// zs = bnd[(pbase + DIR m) / 32] bounds every elevation a lane still reads. Rounding is monotone:
+// be visible on any live lane. zs bounds every elevation a lane still reads: the maximum over the
+// 32-sample blocks from the nearest one at step m to block `bfar`, the farthest any lane of the
+// wavefront reaches within K, read from the range-maximum table `rmq` (two reads, values rounded
+// up to float); for ranges longer than the table covers, or without it, `bnd` holds the maxima
+// accumulated away from the POVs to the row end (suffix maxima forward, prefix maxima
+// backward). Rounding is monotone:
 // for m' >= m, RN(z - h) <= RN(zs - h) and the slope of RN(zs - h) >= 0 does not grow with m', so
 // every remaining slope is at most max(slope(RN(zs - h), m), 0) (a negative difference gives a
 // negative slope). When that bound is <= the lane's horizon, no later target passes the strict
