@@ -389,41 +389,69 @@ template <typename Tz, int DIR, bool RCP, bool PRUNE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
                                               const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
-                                              bool live, int &done) {
+                                              bool live, int own, bool count, int &done, int &skipped) {
     // a lane past the row end starts with a +inf horizon: it never sees a target and never
     // holds back the early exit (its sums are discarded)
     Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
     const int mfull = (mb == K) ? K - 1 : mb;
+    // maximum over blocks lo..hi (1 <= hi - lo + 1 <= 64) from the range table
+    auto range_max = [&](int lo, int hi) -> Tz {
+        const int l = min(31 - __builtin_clz(hi - lo + 1), RMQ_LEVELS - 1);
+        const float *T = rmq + l * nb;
+        float zf;  // the table holds no NaN: a plain max, without canonicalising its inputs
+        asm("v_max_f32 %0, %1, %2" : "=v"(zf) : "v"(T[lo]), "v"(T[hi - (1 << l) + 1]));
+        return (Tz)zf;
+    };
+    // Every slope of steps m' in [m1, m2] whose elevation is at most zs is at most
+    // max(slope(d, m1), slope(d, m2)) with d = RN(zs - h): for d >= 0 the nearest step bounds
+    // it, for d < 0 the farthest (rounding is monotone in both operands).
+    auto bounded_by = [&](Tz zs, int m1, int m2) -> bool {
+        const Tz d = sub_rn(zs, h);
+        const Tz b = vmax(slope<RCP>(d, tab[m1 - 1]), slope<RCP>(d, tab[m2 - 1]));
+        // every lane of the (fully active) wavefront agrees; a wave-uniform answer keeps the
+        // step counter, and with it the table loads, scalar
+        return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
+    };
+    // the wavefront stops: no target from step mm to the last one (mb) can be visible
     auto hidden_from = [&](int mm) -> bool {
         // blocks a lane may still read: from the nearest at step mm to bfar, the farthest any
         // lane of the wavefront reaches within K (the range table), else to the row end
         const int bnear = (pbase + DIR * mm) >> 5;
         const int lo = DIR > 0 ? bnear : bfar, hi = DIR > 0 ? bfar : bnear;
         const int len = hi - lo + 1;
-        Tz zs;
-        if (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) {
-            const int l = min(31 - __builtin_clz(len), RMQ_LEVELS - 1);
-            const float *T = rmq + l * nb;
-            float zf;  // the table holds no NaN: a plain max, without canonicalising its inputs
-            asm("v_max_f32 %0, %1, %2" : "=v"(zf) : "v"(T[lo]), "v"(T[hi - (1 << l) + 1]));
-            zs = (Tz)zf;
+        const Tz zs = (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) ? range_max(lo, hi) : bnd[bnear];
+        return bounded_by(zs, mm, mb);
+    };
+    // the wavefront skips steps mm .. mm + 31: none of their targets can be visible (the blocks
+    // holding them, for all 64 lanes, span at most 95 samples)
+    auto block_hidden = [&](int mm) -> bool {
+        int lo = (pbase + DIR * mm) >> 5, hi = (pbase + DIR * (mm + 94)) >> 5;
+        if (DIR < 0) {
+            const int x = lo;
+            lo = max(hi, 0);
+            hi = x;
         } else {
-            zs = bnd[bnear];
+            hi = min(hi, nb - 1);
         }
-        const Tz b = vmax(slope<RCP>(sub_rn(zs, h), tab[mm - 1]), (Tz)0);
-        // every lane of the (fully active) wavefront agrees; a wave-uniform answer keeps the
-        // step counter, and with it the table loads, scalar
-        return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
+        return bounded_by(range_max(lo, hi), mm, mm + 31);
     };
     RingAcc ra;
     uint32_t bits = 0;
     int m = 1;
     bool stop = false;
+    skipped = 0;
     for (; m + 31 <= mfull; m += 32) {
         if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads on the scalar path
-        if (PRUNE && m > 1 && hidden_from(m)) {
-            stop = true;
-            break;
+        if (PRUNE && m > 1) {
+            if (hidden_from(m)) {
+                stop = true;
+                break;
+            }
+            if (rmq && block_hidden(m)) {
+                // no horizon moves and no bit is set: the block changes nothing
+                if (count) skipped += max(0, min(own, m + 31) - m + 1);
+                continue;
+            }
         }
         const auto *t = static_cast<const typename Tab<Tz>::type *>(__builtin_assume_aligned(tab + (m - 1), 256));
 #pragma unroll
@@ -559,10 +587,14 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         const int bwd = min(K, top);
         int df, db;
         const int bfar_f = min(nb - 1, (q0 + 63 + Kc) >> 5), bfar_b = max(0, q0 - Kc) >> 5;
-        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, live, df);
-        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, live, db);
+        const int own_f = min(K, nt - 1 - q), own_b = min(K, q);  // this lane's last step each way
+        int sf, sb;
+        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, live, own_f, count,
+                                           df, sf);
+        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, live, own_b, count,
+                                           db, sb);
         if (live) dst[q] = U | (e << 30);
-        if (count && live) evals += (uint32_t)(min(df, min(K, nt - 1 - q)) + min(db, min(K, q)));
+        if (count && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
     }
     return evals;
 }
