@@ -442,12 +442,15 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     skipped = 0;
     for (; m + 31 <= mfull; m += 32) {
         if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads on the scalar path
-        if (PRUNE && m > 1) {
+        // The exit test passing implies the skip test passing (its blocks lie inside the exit's
+        // range and its steps inside the remaining ones), so the exit is tested only for blocks
+        // that can be skipped; a block that must be evaluated costs one test.
+        if (PRUNE && m > 1 && (!rmq || block_hidden(m))) {
             if (hidden_from(m)) {
                 stop = true;
                 break;
             }
-            if (rmq && block_hidden(m)) {
+            if (rmq) {
                 // no horizon moves and no bit is set: the block changes nothing
                 if (count) skipped += max(0, min(own, m + 31) - m + 1);
                 continue;
