@@ -212,6 +212,38 @@ def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
                 assert np.array_equal(g, packed(o)), f"k={k} flags={flags}"
 
 
+# Rows long enough to take the sweep's other bound paths: an unbounded distance on 4000-sample rows
+# (ranges beyond the range table's 64 blocks fall back to the row-end maxima), and rows of 18000
+# doubles or 32767 floats, whose LDS leaves no room for the range table (early exit on the row-end
+# maxima alone, no block skipping). Two sectors keep the skewed arrays small (tan s' = 0).
+LONG_ROWS = [(5, 4000, INF, 0, P_DEFAULT), (2, 18000, 2500.0, 0, P_DEFAULT), (3, 32767, 3000.0, F32, P_F32)]
+
+
+@pytest.mark.parametrize("H,W,R,flags,prec", LONG_ROWS)
+def test_long_rows_bound_paths(tvs, orc, H, W, R, flags, prec):
+    # random-walk profiles (a fractal square of side W would take gigabytes)
+    dem = (1000.0 + np.random.default_rng(41).normal(0.0, 4.0, (H, W)).cumsum(axis=1)).astype(np.float32)
+    for k in range(2):
+        note(f"long rows H={H} W={W} R={R} flags={flags} k={k}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, 2, R, k, flags=flags)
+        full = tvs.debug_sector_rays(dem, 10.0, 1.5, 2, R, k, flags=flags | tvs.FLAG_NO_PRUNE)
+        assert np.array_equal(g, full), f"k={k}: pruned and full walks differ"
+        o = orc.sector_V(dem, 10.0, 1.5, 2, R, k, prec=prec)
+        bad = np.argwhere(g != packed(o))
+        assert bad.size == 0, f"k={k}: {len(bad)} samples differ, first {bad[:3].tolist()}"
+    _, st = tvs.total_viewshed(dem, 10.0, 1.5, 2, R, flags=flags | tvs.FLAG_COUNT_EVALS, stats=True)
+    assert 0 < st.sweep_evals_done <= st.los_evals
+
+
+def test_double_rows_beyond_lds_rejected(tvs):
+    """Double rows of 25000 samples (within the side limit) do not fit a workgroup's LDS:
+    TVS_ERANGE, with the float path named in the message."""
+    dem = np.zeros((2, 25000), np.float32)
+    with pytest.raises(tvs.TvsError) as ei:
+        tvs.total_viewshed(dem, 10.0, 1.5, 2, 1000.0)
+    assert ei.value.status == -4 and "TVS_FLAG_SLOPE_F32" in str(ei.value)
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES[:3])
 def test_evaluation_counts(tvs, H, W, n, R, kind):
     """The sweep's own count of evaluations: the closed form without the early exit (and for the
