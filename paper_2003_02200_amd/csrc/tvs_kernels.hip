@@ -389,7 +389,7 @@ template <typename Tz, int DIR, bool RCP, bool PRUNE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
                                               const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
-                                              bool live, int own, bool count, int &done, int &skipped) {
+                                              int q, bool live, int own, bool count, int &done, int &skipped) {
     // a lane past the row end starts with a +inf horizon: it never sees a target and never
     // holds back the early exit (its sums are discarded)
     Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
@@ -422,18 +422,15 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         const Tz zs = (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) ? range_max(lo, hi) : bnd[bnear];
         return bounded_by(zs, mm, mb);
     };
-    // the wavefront skips steps mm .. mm + 31: none of their targets can be visible (the blocks
-    // holding them, for all 64 lanes, span at most 95 samples)
+    // the wavefront skips steps mm .. mm + 31: none of their targets can be visible on any lane.
+    // A lane's 32 targets lie in two consecutive blocks, whose maximum is level 1 of the table
+    // (indices clamped to the row: beyond it lie -inf sentinels, and a lane past the row end has
+    // a +inf horizon).
     auto block_hidden = [&](int mm) -> bool {
-        int lo = (pbase + DIR * mm) >> 5, hi = (pbase + DIR * (mm + 94)) >> 5;
-        if (DIR < 0) {
-            const int x = lo;
-            lo = max(hi, 0);
-            hi = x;
-        } else {
-            hi = min(hi, nb - 1);
-        }
-        return bounded_by(range_max(lo, hi), mm, mm + 31);
+        const int first = DIR > 0 ? q + mm : q - mm - 31;  // the lane's lowest target position
+        const int b = min(max(first >> 5, 0), nb - 1);
+        const float zf = rmq[nb + b];
+        return bounded_by((Tz)zf, mm, mm + 31);
     };
     RingAcc ra;
     uint32_t bits = 0;
@@ -592,10 +589,10 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         const int bfar_f = min(nb - 1, (q0 + 63 + Kc) >> 5), bfar_b = max(0, q0 - Kc) >> 5;
         const int own_f = min(K, nt - 1 - q), own_b = min(K, q);  // this lane's last step each way
         int sf, sb;
-        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, live, own_f, count,
-                                           df, sf);
-        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, live, own_b, count,
-                                           db, sb);
+        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, q, live, own_f,
+                                           count, df, sf);
+        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, q, live, own_b,
+                                           count, db, sb);
         if (live) dst[q] = U | (e << 30);
         if (count && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
     }
