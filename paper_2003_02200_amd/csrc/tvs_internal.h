@@ -7,7 +7,7 @@
 #include "tvs_geom.h"
 
 // Sectors processed by one group of launches; their parameters travel as kernel arguments
-// (48 x 48 B), so the library needs no host-to-device copy besides the caller's data.
+// (48 x 56 B), so the library needs no host-to-device copy besides the caller's data.
 #define TVS_CHUNK 48
 // Sentinel columns on each side of a skewed row held in LDS by the sweep: a wavefront's 64
 // lines of sight all stop at the same step, so lanes whose row ends earlier (at most 63 steps
@@ -42,6 +42,8 @@ struct ChunkArgs {
     int32_t rmq;    // sweep: 1 when the early exit's range-maximum table is in LDS (set by launch_sweep)
     int32_t pad1;
 };
+static_assert(sizeof(SecDev) == 56, "sector parameters: 56 bytes");
+static_assert(sizeof(ChunkArgs) <= 4096, "chunk parameters must fit the kernel argument space");
 
 // One (tile, sector) of a batch chunk: the sector's geometry (off = element offset of its skewed
 // viewshed rows in the chunk buffer) and the tile it belongs to.
