@@ -191,6 +191,17 @@ def main():
         "scratch_bytes": st.scratch_bytes,
     }
 
+    # the host entry point (DEM in host memory, map back to host memory): PCIe transfers, host-side
+    # validation and device scratch included; reported beside `value`, never as it
+    host_ms = None
+    if args.flags == 0:
+        tvs.total_viewshed(dem, *call)
+        t1 = time.perf_counter()
+        for _ in range(2):
+            tvs.total_viewshed(dem, *call)
+        host_ms = (time.perf_counter() - t1) / 2 * 1e3
+        log(f"host entry point: {host_ms:.2f} ms per call")
+
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
@@ -241,6 +252,13 @@ def main():
             "flags": args.flags, "los_evals_per_step": evals, "pov_sector_pairs_per_step": pairs,
         },
         "total_viewshed_cells_per_s": H * W / step_s,
+        "host_api": None if host_ms is None else {
+            "ms_per_call": host_ms, "total_viewshed_cells_per_s": H * W / (host_ms / 1e3),
+            "note": "tvs_total_viewshed with the DEM and map in host memory: PCIe copies and host-side "
+                    "validation included"},
+        # evaluations decided per second against an exhaustive sweep at the ALU peak (5 ops per
+        # evaluation): above 1 only through the exact early exit and block skipping
+        "evals_vs_exhaustive_alu_peak": (evals * args.steps / elapsed) / (ALU_PEAK_OPS / OPS_PER_EVAL),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
