@@ -104,6 +104,16 @@ int check_scalars(int rows, int cols, double dx, double h0, int n, double R) {
 
 int check_host_dem(const float *dem, int rows, int cols) {
     const int64_t N = (int64_t)rows * cols;
+    // a vectorisable pass on the bit patterns first: a non-finite value has exponent field 255; a
+    // nonzero magnitude below 2^-60 has a biased exponent below 127 - 60
+    uint32_t bad = 0;
+    for (int64_t x = 0; x < N; ++x) {
+        uint32_t u;
+        memcpy(&u, dem + x, sizeof(u));
+        const uint32_t e = (u >> 23) & 0xFFu;
+        bad |= (uint32_t)(e == 0xFFu) | ((uint32_t)(e < 67u) & (uint32_t)((u & 0x7FFFFFFFu) != 0u));
+    }
+    if (!bad) return TVS_OK;
     for (int64_t x = 0; x < N; ++x)
         if (!isfinite(dem[x]) || !magnitude_ok(dem[x]))
             return fail(TVS_EINVAL, "elevation %g at cell (%lld, %lld) is not finite, or is nonzero below 2^-60 m",
@@ -514,13 +524,20 @@ int run_multi(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     return TVS_OK;
 }
 
+// Device buffer of the synchronous host entry points: taken from the device's stream-ordered pool on
+// the null stream (which keeps freed memory, so repeated calls do not map and unmap it) and returned
+// there; the entry points copy with hipMemcpy, ordered on the same stream.
 template <typename T>
 struct DevBuf {
     T *p = nullptr;
     ~DevBuf() {
-        if (p) (void)hipFree(p);
+        if (p) (void)hipFreeAsync(p, nullptr);
     }
-    hipError_t alloc(size_t n) { return hipMalloc((void **)&p, n * sizeof(T)); }
+    hipError_t alloc(size_t n) {
+        int dev = 0;
+        if (hipGetDevice(&dev) == hipSuccess) pool_keep_memory(dev);
+        return hipMallocAsync((void **)&p, n * sizeof(T), nullptr);
+    }
 };
 
 }  // namespace

@@ -142,3 +142,23 @@ def test_batch_rejects_bad_arguments(tvs):
     assert L.tvs_batch_run(None, None) == -1
     assert L.tvs_batch_destroy(None) == 0
     assert L.tvs_total_viewshed_tiles(None, 1, 8, 0, None) == -1
+
+
+def test_host_elevation_check_boundaries(tvs):
+    """The host entry point's elevation check (finite, and 0 or at least 2^-60 m in magnitude) at its
+    boundaries: rejected values give TVS_EINVAL naming the cell; accepted grids pass validation
+    (what follows needs a device, so only the absence of TVS_EINVAL is checked)."""
+    L = tvs.lib()
+    vp = C.c_void_p
+    out = np.zeros(12, np.float64)
+    lim = np.float32(2.0 ** -60)
+    for v, ok in ((lim, True), (-lim, True), (np.float32(-0.0), True), (np.float32(3.0e38), True),
+                  (np.nextafter(lim, np.float32(0)), False), (np.float32(-1e-30), False),
+                  (np.float32(1e-45), False), (np.float32(np.nan), False), (np.float32(-np.inf), False)):
+        d = np.full((3, 4), 7.0, np.float32)
+        d[2, 3] = v
+        rc = L.tvs_total_viewshed(d.ctypes.data_as(vp), 3, 4, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp))
+        if ok:
+            assert rc != -1, (v, L.tvs_last_error())
+        else:
+            assert rc == -1 and b"(2, 3)" in L.tvs_last_error(), v
