@@ -195,9 +195,11 @@ std::vector<Chunk> make_chunks(const std::vector<Sector> &S, size_t elem, int pi
     std::vector<Chunk> out;
     int k = 0;
     const int n = (int)S.size();
+    // as few chunks as TVS_CHUNK allows, of even size (180 sectors: 3 x 60, not 72 + 72 + 36)
+    const int per = n > 0 ? (n + (n + TVS_CHUNK - 1) / TVS_CHUNK - 1) / ((n + TVS_CHUNK - 1) / TVS_CHUNK) : 1;
     while (k < n) {
         Chunk c{k, k, 0, 0, 0};
-        while (c.k1 < n && c.k1 - c.k0 < TVS_CHUNK) {
+        while (c.k1 < n && c.k1 - c.k0 < per) {
             const size_t b = (size_t)S[c.k1].prows * pitch * (elem + sizeof(uint32_t));
             if (c.k1 > c.k0 && c.bytes + b > budget) break;
             c.bytes += b;

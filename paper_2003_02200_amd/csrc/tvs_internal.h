@@ -7,8 +7,8 @@
 #include "tvs_geom.h"
 
 // Sectors processed by one group of launches; their parameters travel as kernel arguments
-// (48 x 56 B), so the library needs no host-to-device copy besides the caller's data.
-#define TVS_CHUNK 48
+// (72 x 56 B), so the library needs no host-to-device copy besides the caller's data.
+#define TVS_CHUNK 72
 // Sentinel columns on each side of a skewed row held in LDS by the sweep: a wavefront's 64
 // lines of sight all stop at the same step, so lanes whose row ends earlier (at most 63 steps
 // earlier) read these.
