@@ -39,10 +39,17 @@ def log(*a):
 
 
 def kernel_source_digest():
+    """Hash of every library source: kernels, launch plan (chunking) and host code all change the
+    bytes a launch moves."""
+    import glob
     import hashlib
 
-    path = os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "tvs_kernels.hip")
-    return hashlib.sha256(open(path, "rb").read()).hexdigest()
+    h = hashlib.sha256()
+    for path in sorted(glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.h")) +
+                       glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.hip"))):
+        h.update(os.path.basename(path).encode())
+        h.update(open(path, "rb").read())
+    return h.hexdigest()
 
 
 def read_traffic(path, workload, flags):
@@ -57,7 +64,7 @@ def read_traffic(path, workload, flags):
             k, v = line[2:].split(":", 1)
             fields[k.strip()] = v.strip().strip("`")
     try:
-        if (fields.get("kernel_source_sha256") != kernel_source_digest() or fields.get("workload") != workload
+        if (fields.get("library_source_sha256") != kernel_source_digest() or fields.get("workload") != workload
                 or int(fields.get("flags", "-1")) != flags):
             return None
         return int(fields["hbm_read_bytes_per_launch"]) + int(fields["hbm_write_bytes_per_launch"])
