@@ -126,6 +126,18 @@ __device__ __forceinline__ double dpp_mov(double old, double x) {
     return *reinterpret_cast<const double *>(&res);
 }
 template <typename T> __device__ __forceinline__ T vmax(T a, T b) { return a > b ? a : b; }
+// max of two values known not to be NaN, as one instruction (the compare-and-select form above
+// takes three for doubles)
+__device__ __forceinline__ double vmax_plain(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ float vmax_plain(float a, float b) {
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
 
 // Inclusive prefix maximum over the 64 lanes (lane l gets max of lanes 0..l).
 template <typename T>
@@ -407,7 +419,7 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     // it, for d < 0 the farthest (rounding is monotone in both operands).
     auto bounded_by = [&](Tz zs, int m1, int m2) -> bool {
         const Tz d = sub_rn(zs, h);
-        const Tz b = vmax(slope<RCP>(d, tab[m1 - 1]), slope<RCP>(d, tab[m2 - 1]));
+        const Tz b = vmax_plain(slope<RCP>(d, tab[m1 - 1]), slope<RCP>(d, tab[m2 - 1]));
         // every lane of the (fully active) wavefront agrees; a wave-uniform answer keeps the
         // step counter, and with it the table loads, scalar
         return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
@@ -467,7 +479,7 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         for (; m <= mfull; ++m) {
             const Tz th = slope<RCP>(sub_rn(zp[DIR * m], h), tab[m - 1]);
             acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
-            mx = vmax(mx, th);
+            mx = vmax_plain(mx, th);
         }
         if (mb == K && K >= 1) e = slope<RCP>(sub_rn(zp[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
     }
