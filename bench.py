@@ -39,8 +39,9 @@ def log(*a):
 
 
 def kernel_source_digest():
-    """Hash of every library source: kernels, launch plan (chunking) and host code all change the
-    bytes a launch moves."""
+    """Hash of the code of every library source (kernels, launch plan and host code all change the
+    bytes a launch moves), without its // comments and blank lines, so that edits to comments keep
+    a traffic summary valid. The sources hold no "//" inside string literals."""
     import glob
     import hashlib
 
@@ -48,7 +49,10 @@ def kernel_source_digest():
     for path in sorted(glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.h")) +
                        glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.hip"))):
         h.update(os.path.basename(path).encode())
-        h.update(open(path, "rb").read())
+        for line in open(path, encoding="utf-8"):
+            code = line.split("//", 1)[0].rstrip()
+            if code:
+                h.update(code.encode() + b"\n")
     return h.hexdigest()
 
 
