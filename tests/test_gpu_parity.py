@@ -305,6 +305,18 @@ def test_compact_layout_many_chunks(tvs, monkeypatch):
     assert np.array_equal(plain, ref) and np.array_equal(comp, ref)
 
 
+@pytest.mark.parametrize("n", [72, 73, 144])
+def test_total_full_chunks(tvs, orc, n):
+    """Sector counts at the chunk capacity (72 sectors in the kernel arguments: the last entries and
+    the pointers after them lie past 4 KB of arguments) and just beyond it, against the oracle."""
+    dem = _dem(41, 37, "fractal", seed=23)
+    for flags, prec in (MODES[0], MODES[2]):
+        note(f"full chunks n={n} flags={flags}")
+        g, st = tvs.total_viewshed(dem, 10.0, 1.5, n, 333.0, flags=flags, stats=True)
+        assert st.chunks == (n + 71) // 72
+        np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, 333.0, prec=prec), rtol=1e-12, atol=0)
+
+
 def test_flat_full_disc_on_gpu(tvs):
     """P1 through the GPU: interior cells of flat ground get pi R^2."""
     H = W = 90
