@@ -86,10 +86,11 @@ def main():
     ap.add_argument("--cpu-window", type=int, default=128, help="side of the centre window the oracle times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic-summary", default=os.path.join(ROOT, "profiles", "sweep_tvs2000_traffic.md"))
-    ap.add_argument("--mode", choices=("single", "batch", "serve"), default="single",
+    ap.add_argument("--mode", choices=("single", "batch", "serve", "multiple"), default="single",
                     help="single: the 2000x2000 workload (the headline); batch: 64 independent tiles of uneven "
                          "size through the batched path, against the plain per-tile loop; serve: a Poisson stream "
-                         "of singular and total requests through the request server")
+                         "of singular and total requests through the request server; multiple: the count map of "
+                         "10 random POVs on the 2000x2000 workload, against 10 singular calls")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--batch-tiles", type=int, default=64)
@@ -114,6 +115,8 @@ def main():
         return bench_batch(args)
     if args.mode == "serve":
         return bench_serve(args)
+    if args.mode == "multiple":
+        return bench_multiple(args)
 
     w = WORKLOADS[args.workload]
     dem = workload_dem(args.workload)
@@ -341,6 +344,51 @@ def bench_batch(args):
     }
     batch.close()
     print(json.dumps(line), flush=True)
+
+
+def bench_multiple(args):
+    """Multiple viewshed (Section 5.3's GIS comparison shape): per cell, how many of 10 random POVs
+    see it, on the 2000x2000 workload, in one call; timed against 10 singular viewshed calls."""
+    import numpy as np
+    import torch
+
+    import paper_2003_02200_amd as tvs
+    from synth import WORKLOADS, workload_dem
+
+    w = WORKLOADS["tvs2000"]
+    torch.cuda.set_device(0)
+    d = torch.from_numpy(workload_dem("tvs2000")).cuda()
+    rng = np.random.default_rng(2020)
+    povs = [(int(rng.integers(0, 2000)), int(rng.integers(0, 2000))) for _ in range(10)]
+    call = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+
+    def timed(fn, k):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k
+
+    mult_s = timed(lambda: tvs.multiple_viewshed(d, *call, povs), args.steps)
+
+    def singles():
+        for (i, j) in povs:
+            tvs.singular_viewshed(d, *call, i, j)
+
+    sing_s = timed(singles, args.steps)
+    cnt = tvs.multiple_viewshed(d, *call, povs)
+    torch.cuda.synchronize()
+    seen = int((cnt.cpu().numpy().view(np.uint32) > 0).sum())
+    log(f"multiple viewshed of 10 POVs: {mult_s * 1e3:.2f} ms; 10 singular areas: {sing_s * 1e3:.2f} ms")
+    print(json.dumps({
+        "metric": "multiple viewshed latency (count map of 10 POVs)", "value": mult_s * 1e3, "unit": "ms",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1, "ms_per_step": mult_s * 1e3, "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "tvs2000 grid, 10 random POVs (seed 2020), 180 sectors, 10 km"},
+        "ten_singular_areas_ms": sing_s * 1e3, "cells_seen_by_any": seen,
+    }), flush=True)
 
 
 def bench_serve(args):
