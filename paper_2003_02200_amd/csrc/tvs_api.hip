@@ -12,6 +12,7 @@
 #include <cstring>
 
 #include <algorithm>
+#include <atomic>
 #include <vector>
 
 #include "../../include/libtvs.h"
@@ -158,14 +159,14 @@ size_t scratch_budget() {
 }
 
 void pool_keep_memory(int dev) {
-    static bool done[64] = {false};
-    if (dev < 0 || dev >= 64 || done[dev]) return;
+    static std::atomic<bool> done[64];  // calls come from any thread (the request server's included)
+    if (dev < 0 || dev >= 64 || done[dev].load(std::memory_order_acquire)) return;
     hipMemPool_t pool;
     if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
         uint64_t thr = UINT64_MAX;
         (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
     }
-    done[dev] = true;
+    done[dev].store(true, std::memory_order_release);
 }
 
 int lds_limit(int dev) {

@@ -31,6 +31,8 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <mutex>
+#include <unordered_map>
 #include <math.h>
 #include <stdint.h>
 
@@ -1179,8 +1181,13 @@ static size_t sweep_lds_launch(int maxWx, bool f64, int &rmq) {
     int dev = 0, cap = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
         cap = caps[dev].load();
-        if (cap == 0 && hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess)
-            caps[dev].store(cap);
+        if (cap == 0) {
+            // the same limit the host checks use: the opt-in maximum, else the default one
+            if (hipDeviceGetAttribute(&cap, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || cap <= 0)
+                if (hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+                    cap = 0;
+            if (cap > 0) caps[dev].store(cap);
+        }
     }
     rmq = full + 64 <= (size_t)cap ? 1 : 0;  // + the kernels' static LDS
     return rmq ? full : base;
@@ -1205,11 +1212,21 @@ hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const flo
     return hipGetLastError();
 }
 
+// A kernel's dynamic LDS limit only ever rises (under a lock): a launch from another host thread
+// with a smaller row never lowers it under a launch that needs more.
+static std::mutex g_lds_mu;
+static std::unordered_map<const void *, size_t> g_lds_set;
+
 template <typename F>
 static hipError_t set_lds(F f, size_t bytes) {
     if (bytes <= 65536) return hipSuccess;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(f), hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)bytes);
+    const void *key = reinterpret_cast<const void *>(f);
+    std::lock_guard<std::mutex> g(g_lds_mu);
+    size_t &cur = g_lds_set[key];
+    if (cur >= bytes) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
 }
 
 template <typename Tz>
