@@ -43,7 +43,7 @@ struct ChunkArgs {
     int32_t pad1;
 };
 static_assert(sizeof(SecDev) == 56, "sector parameters: 56 bytes");
-static_assert(sizeof(ChunkArgs) <= 4096, "a chunk's parameters stay within 4 KB of kernel arguments");
+static_assert(sizeof(ChunkArgs) <= 4096, "chunk parameters must fit the kernel argument space");
 
 // One (tile, sector) of a batch chunk: the sector's geometry (off = element offset of its skewed
 // viewshed rows in the chunk buffer) and the tile it belongs to.
