@@ -500,6 +500,29 @@ def _flip_scan(tvs, orc, d, args, flags_a, flags_b):
     return flips, pairs, fed
 
 
+def test_workload_8000_sampled(tvs, orc):
+    """The 8000 x 8000 grid (the largest grid shape of Table 2) in the bench's launch configuration:
+    sampled cells against the oracle taking the same decisions, plus properties that hold at any size."""
+    import torch
+
+    w = WORKLOADS["tvs8000"]
+    dem = workload_dem("tvs8000")
+    args = (w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"])
+    note("workload tvs8000 total (device-resident)")
+    out = tvs.total_viewshed(torch.from_numpy(dem).cuda(), *args)
+    torch.cuda.synchronize()
+    g = out.cpu().numpy()
+    del out
+    R = w["max_dist"]
+    assert np.all(np.isfinite(g)) and np.all(g > 0) and np.all(g <= math.pi * R * R * (1 + 1e-12))
+    rng = np.random.default_rng(8000)
+    cells = [(0, 0), (0, 7999), (7999, 0), (7999, 7999), (4000, 4000), (7998, 5), (2, 6000)]
+    cells += [tuple(int(x) for x in rng.integers(0, 8000, 2)) for _ in range(13)]
+    for (i, j) in cells:
+        o = orc.total(dem, *args, prec=P_DEFAULT, window=(i, j, 1, 1))[0, 0]
+        assert abs(g[i, j] - o) <= 1e-12 * o, (i, j, g[i, j], o)
+
+
 def test_workload_2000_crop_against_double_oracle(tvs, orc):
     """The 2000 x 2000, 180-sector workload against the double oracle on the 256 x 256 centre crop
     (R23), with horizon flips counted over all 7.2e8 POV-sector pairs against the GPU double
