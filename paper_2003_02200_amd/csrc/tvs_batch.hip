@@ -247,7 +247,7 @@ hipError_t enqueue_pass(tvs_batch *b, hipStream_t st) {
         const ChunkPlan &c = b->chunks[ci];
         if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + c.item_off, c.nitems, b->counters + ci, b->V,
                                     b->tab32, b->tab64, b->f64, b->rcp, b->shape.waves, b->grid, b->maxWx,
-                                    b->count ? b->work : nullptr, st)) != hipSuccess)
+                                    b->maxK, b->count ? b->work : nullptr, st)) != hipSuccess)
             return e;
         if ((e = launch_backproj_batch(b->btiles + c.tile_off, b->ntiles, c.nblocks, b->ent + c.ent_off,
                                        c.k1 - c.k0, b->V, ci == 0, st)) != hipSuccess)
@@ -287,11 +287,11 @@ int autotune(tvs_batch *b, int cus) {
             float ms = 0.f;
             for (int rep = 0; rep < 2 && rc == TVS_OK; ++rep) {  // the first run warms the caches
                 if (launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
-                                       s.waves, 0, b->maxWx, nullptr, b->cap) != hipSuccess ||
+                                       s.waves, 0, b->maxWx, b->maxK, nullptr, b->cap) != hipSuccess ||
                     launch_fill_u32(d_ctr, 1, 0u, b->cap) != hipSuccess || hipEventRecord(e0, b->cap) != hipSuccess ||
                     launch_sweep_batch(b->ent + c.ent_off, d_sample, (int)sample.size(), d_ctr, b->V, b->tab32,
-                                       b->tab64, b->f64, b->rcp, s.waves, grid, b->maxWx, nullptr,
-                                       b->cap) != hipSuccess ||
+                                       b->tab64, b->f64, b->rcp, s.waves, grid, b->maxWx, b->maxK,
+                                       nullptr, b->cap) != hipSuccess ||
                     hipEventRecord(e1, b->cap) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                     rc = fail(TVS_EDEVICE, "autotune run failed: %s", hipGetErrorString(hipGetLastError()));
@@ -392,7 +392,7 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     b->grid = cus * b->shape.per_cu;
     // raise the sweep's LDS limit before capture (no attribute calls inside a graph)
     HIPCHK(launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
-                              b->shape.waves, 0, b->maxWx, nullptr, b->cap));
+                              b->shape.waves, 0, b->maxWx, b->maxK, nullptr, b->cap));
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     const hipError_t le = enqueue_pass(b, b->cap);
     const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);

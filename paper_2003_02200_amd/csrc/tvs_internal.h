@@ -101,7 +101,8 @@ hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
 // grid == 0 only prepares the kernel's LDS limit.
 hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
-                              int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st);
+                              int waves, int grid, int maxWx, int maxK, unsigned long long *work,
+                              hipStream_t st);
 hipError_t launch_backproj_batch(const BatchTile *tiles, int ntiles, int nblocks, const BatchEnt *ent, int nsec,
                                  const uint32_t *V, int first, hipStream_t st);
 // Every query's 2 * nsec lines of sight, then each query's area (in sector order). With `bits`

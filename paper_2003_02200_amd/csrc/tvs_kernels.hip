@@ -401,11 +401,14 @@ struct RingAcc {
 // every remaining slope is at most max(slope(RN(zs - h), m), 0) (a negative difference gives a
 // negative slope). When that bound is <= the lane's horizon, no later target passes the strict
 // test, the clipped last ring included, and the ring sums are those of the full walk.
-template <typename Tz, int DIR, bool RCP, bool PRUNE>
+// With SLIDE the skip test reads the sliding maxima `slide` instead of the table's level 1, and
+// the launch keeps every exit range within the table (there is no `bnd`).
+template <typename Tz, int DIR, bool RCP, bool PRUNE, bool SLIDE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
                                               const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
-                                              int q, bool live, int own, bool count, int &done, int &skipped) {
+                                              int q, bool live, int own, bool count, int &done, int &skipped,
+                                              const float *slide) {
     // a lane past the row end starts with a +inf horizon: it never sees a target and never
     // holds back the early exit (its sums are discarded)
     Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
@@ -435,17 +438,27 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         const int bnear = (pbase + DIR * mm) >> 5;
         const int lo = DIR > 0 ? bnear : bfar, hi = DIR > 0 ? bfar : bnear;
         const int len = hi - lo + 1;
-        const Tz zs = (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) ? range_max(lo, hi) : bnd[bnear];
+        // (with SLIDE a range past the table bounds nothing: +inf, and the wavefront walks on)
+        const Tz zs = (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) ? range_max(lo, hi)
+                      : SLIDE                                              ? -neg_inf<Tz>()
+                                                                           : bnd[bnear];
         return bounded_by(zs, mm, mb);
     };
     // the wavefront skips steps mm .. mm + 31: none of their targets can be visible on any lane.
-    // A lane's 32 targets lie in two consecutive blocks, whose maximum is level 1 of the table
-    // (indices clamped to the row: beyond it lie -inf sentinels, and a lane past the row end has
-    // a +inf horizon).
+    // A lane's 32 targets lie in two consecutive blocks, whose maximum is level 1 of the table;
+    // with SLIDE, in the 40 samples from the 8-aligned position at or before the first, whose
+    // maximum is slide[first >> 3] (indices clamped to the row: a clamped entry still covers
+    // every target inside it, beyond it lie -inf sentinels, and a lane past the row end has a
+    // +inf horizon).
     auto block_hidden = [&](int mm) -> bool {
         const int first = DIR > 0 ? q + mm : q - mm - 31;  // the lane's lowest target position
-        const int b = min(max(first >> 5, 0), nb - 1);
-        const float zf = rmq[nb + b];
+        float zf;
+        if constexpr (SLIDE) {
+            zf = slide[min(max(first >> 3, 0), 4 * nb - 1)];
+        } else {
+            const int b = min(max(first >> 5, 0), nb - 1);
+            zf = rmq[nb + b];
+        }
         return bounded_by((Tz)zf, mm, mm + 31);
     };
     RingAcc ra;
@@ -500,20 +513,60 @@ __device__ __forceinline__ float ru_float(double x) {
 }
 __device__ __forceinline__ float ru_float(float x) { return x; }
 
+// Maxima of the row's samples 8k .. 8k + 39 (sentinels past the row end), rounded up to float, at
+// slide[k] for k < 4 nb. A wavefront reads 64 consecutive samples; three row shifts leave the
+// maximum of each group of 8 lanes in its last lane. Then each entry takes the maximum of itself
+// and the next four, in tiles of one workgroup: a tile reads before any of its entries is
+// written, and later tiles read only entries at or beyond their own.
+template <typename Tz>
+__device__ void sliding_max40(const Tz *z, int nb, float *slide) {
+    const int lane = threadIdx.x & 63;
+    const int nw = blockDim.x >> 6;
+    const int n8 = nb << 2;
+    const Tz lo = neg_inf<Tz>();
+    // c + 63 <= 32 nb + 31 <= nt + 62: inside the sentinels
+    for (int c = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) << 6; c < n8 << 3; c += nw << 6) {
+        Tz x = z[c + lane];
+        x = vmax(x, dpp_mov<0x111>(lo, x));  // row_shr:1
+        x = vmax(x, dpp_mov<0x112>(lo, x));  // row_shr:2
+        x = vmax(x, dpp_mov<0x114>(lo, x));  // row_shr:4
+        const int k = (c + lane) >> 3;
+        if ((lane & 7) == 7 && k < n8) slide[k] = ru_float(x);
+    }
+    __syncthreads();
+    for (int t0 = 0; t0 < n8; t0 += blockDim.x) {
+        const int k = t0 + threadIdx.x;
+        float v = neg_inf<float>();
+        if (k < n8) {
+            v = slide[k];
+#pragma unroll
+            for (int i = 1; i <= 4; ++i)
+                if (k + i < n8) v = fmaxf(v, slide[k + i]);
+        }
+        __syncthreads();
+        if (k < n8) slide[k] = v;
+        __syncthreads();
+    }
+}
+
 // Per-block elevation maxima of a row of nt samples (followed by -inf sentinels): pre[b] is the
 // maximum over blocks 0..b, suf[b] over blocks b..nb-1, each scanned by one wavefront with the
 // wavefront prefix-max. With `rmq`, level l of the table holds at rmq[l nb + b] the maximum over
-// blocks b .. min(b + 2^l, nb) - 1, rounded up to float.
-template <typename Tz>
-__device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq) {
+// blocks b .. min(b + 2^l, nb) - 1, rounded up to float. With SLIDE the table and the sliding
+// maxima of 40 samples are built instead (no suf and pre).
+template <typename Tz, bool SLIDE>
+__device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq, float *slide) {
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         Tz m = z[32 * b];
 #pragma unroll
         for (int i = 1; i < 32; ++i) m = vmax(m, z[32 * b + i]);
-        suf[b] = m;
-        pre[b] = m;
+        if constexpr (!SLIDE) {
+            suf[b] = m;
+            pre[b] = m;
+        }
         if (rmq) rmq[b] = ru_float(m);
     }
+    if constexpr (SLIDE) sliding_max40(z, nb, slide);  // its barriers also order the table's first level
     __syncthreads();
     if (rmq) {
         for (int l = 1; l < RMQ_LEVELS; ++l) {
@@ -526,7 +579,7 @@ __device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq) 
     }
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    if (wv < 2) {
+    if (!SLIDE && wv < 2) {
         Tz *arr = wv == 0 ? pre : suf;
         Tz carry = neg_inf<Tz>();
         for (int c = 0; c < nb; c += 64) {
@@ -575,16 +628,27 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
 
 // Sweeps a skewed row of nt samples held in LDS (row[TVS_SWEEP_PAD + q], -inf sentinels on both
 // sides, room for the early exit's block maxima after them) and stores U | e << 30 of POV q at
-// dst[q]. Returns the evaluations this lane carried out when `count` is set.
-template <typename Tz, int NW, bool RCP, bool PRUNE>
+// dst[q]. Returns the evaluations this lane carried out when `count` is set. After the row lie
+// the suffix and prefix block maxima, then (use_rmq) the range-maximum table; with SLIDE the
+// table, then the sliding maxima of 40 samples at every 8th position.
+template <typename Tz, int NW, bool RCP, bool PRUNE, bool SLIDE = false>
 __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                               const typename Tab<Tz>::type *__restrict__ tab,
                                               uint32_t *__restrict__ dst, bool count, bool use_rmq) {
     const int nb = (nt + 31) >> 5;
-    Tz *suf = row + nt + 2 * TVS_SWEEP_PAD;
-    Tz *pre = suf + nb;
-    float *rmq = use_rmq ? reinterpret_cast<float *>(pre + nb) : nullptr;
-    if (PRUNE) block_bounds(row + TVS_SWEEP_PAD, nb, suf, pre, rmq);
+    Tz *suf = nullptr, *pre = nullptr;
+    float *rmq, *slide = nullptr;
+    if constexpr (SLIDE) {
+        // launches with SLIDE set use_rmq; a pointer the compiler cannot prove non-null keeps the
+        // block loop's ring sums in place (proven, its loop copies them on every block)
+        rmq = use_rmq ? reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) : nullptr;
+        slide = reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) + RMQ_LEVELS * nb;
+    } else {
+        suf = row + nt + 2 * TVS_SWEEP_PAD;
+        pre = suf + nb;
+        rmq = use_rmq ? reinterpret_cast<float *>(pre + nb) : nullptr;
+    }
+    if (PRUNE) block_bounds<Tz, SLIDE>(row + TVS_SWEEP_PAD, nb, suf, pre, rmq, slide);
     const int Kc = min(K, nt);  // K may be unbounded
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -605,10 +669,10 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         const int bfar_f = min(nb - 1, (q0 + 63 + Kc) >> 5), bfar_b = max(0, q0 - Kc) >> 5;
         const int own_f = min(K, nt - 1 - q), own_b = min(K, q);  // this lane's last step each way
         int sf, sb;
-        e += sweep_dir<Tz, +1, RCP, PRUNE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, q, live, own_f,
-                                           count, df, sf);
-        e += sweep_dir<Tz, -1, RCP, PRUNE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, q, live, own_b,
-                                           count, db, sb);
+        e += sweep_dir<Tz, +1, RCP, PRUNE, SLIDE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, q, live,
+                                                  own_f, count, df, sf, slide);
+        e += sweep_dir<Tz, -1, RCP, PRUNE, SLIDE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, q, live,
+                                                  own_b, count, db, sb, slide);
         if (live) dst[q] = U | (e << 30);
         if (count && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
     }
@@ -626,7 +690,7 @@ __device__ __forceinline__ void add_work(unsigned long long *work, unsigned long
     if (threadIdx.x == 0) atomicAdd(&work[slot & 63], wg_work);
 }
 
-template <typename Tz, int NW, bool RCP, bool PRUNE>
+template <typename Tz, int NW, bool RCP, bool PRUNE, bool SLIDE = false>
 __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
                                                    const typename Tab<Tz>::type *__restrict__ tab,
@@ -641,9 +705,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
     const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
     if (nt == 0) return;
     if (work && threadIdx.x == 0) wg_work = 0;
-    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE>(row, nt, s.K, h0_of<Tz>(a), tab,
-                                                         V + skw_row(s, s.t0 + ri, a.pitch) + jlo,
-                                                         work != nullptr, a.rmq != 0);
+    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE, SLIDE>(row, nt, s.K, h0_of<Tz>(a), tab,
+                                                                V + skw_row(s, s.t0 + ri, a.pitch) + jlo,
+                                                                work != nullptr, a.rmq != 0);
     if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
@@ -692,7 +756,7 @@ template <> __device__ __forceinline__ double h0_of<double>(const BatchEnt &e) {
 // Persistent sweep over every (tile, sector, skewed row) item of a batch chunk: each workgroup
 // takes the next item from a device counter until the list is exhausted (every workgroup
 // reaches the end, the counter only grows), gathers the row from its tile's DEM and sweeps it.
-template <typename Tz, int NW, bool RCP>
+template <typename Tz, int NW, bool RCP, bool SLIDE = false>
 __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restrict__ ent,
                                                          const uint32_t *__restrict__ items, int nitems,
                                                          unsigned int *__restrict__ counter, uint32_t *__restrict__ V,
@@ -716,9 +780,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         int jlo;
         const int nt = gather_row<Tz>(E.dem, E.H, E.W, E.s, ri, row, jlo);
         if (nt > 0)
-            evals += sweep_row<Tz, NW, RCP, true>(row, nt, E.s.K, h0_of<Tz>(E), tab,
-                                                  V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
-                                                  work != nullptr, rmq != 0);
+            evals += sweep_row<Tz, NW, RCP, true, SLIDE>(row, nt, E.s.K, h0_of<Tz>(E), tab,
+                                                         V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
+                                                         work != nullptr, rmq != 0);
         __syncthreads();  // the row is read by every wavefront before the next gather
     }
     if (work) add_work(work, wg_work, evals, blockIdx.x);
@@ -1171,6 +1235,12 @@ size_t sweep_lds_bytes(int maxWx, bool f64) {
     return (size_t)(maxWx + 2 * TVS_SWEEP_PAD + 2 * ((maxWx + 31) / 32)) * (f64 ? sizeof(double) : sizeof(float));
 }
 
+// Largest step count (K capped at the row length) for which every early-exit range of a
+// wavefront, from the block of its nearest remaining target to the farthest block its lanes
+// reach, spans at most the 64 blocks the range-maximum table covers: fewer than (K + 62) / 32 + 2
+// blocks. Launches within it may use the sliding maxima, which need no suffix or prefix maxima.
+constexpr int SLIDE_MAX_K = 1900;
+
 // The sweep's LDS with the early exit's range-maximum table when it fits the workgroup limit
 // (rmq = 1), else without it (rmq = 0).
 static size_t sweep_lds_launch(int maxWx, bool f64, int &rmq) {
@@ -1243,7 +1313,11 @@ static hipError_t sweep_go(void (*f)(ChunkArgs, const Tz *, uint32_t *, const ty
 template <int NW>
 static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void *skw, uint32_t *V,
                            const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
-                           unsigned long long *work, hipStream_t st) {
+                           bool slide, unsigned long long *work, hipStream_t st) {
+    if (f64 && slide) {
+        auto f = rcp ? k_sweep<double, NW, true, true, true> : k_sweep<double, NW, false, true, true>;
+        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+    }
     if (f64) {
         auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
                  : rcp ? (prune ? k_sweep<double, NW, true, true> : k_sweep<double, NW, true, false>)
@@ -1273,10 +1347,14 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
     const dim3 grid(maxRows, a.nsec);
     ChunkArgs b = a;
     const size_t lds = sweep_lds_launch(maxWx, f64, b.rmq);
+    // the sliding maxima take the LDS of the suffix and prefix maxima of double rows
+    int maxK = 0;
+    for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
+    const bool slide = f64 && prune && !scan && b.rmq && maxK <= SLIDE_MAX_K;
     switch (sweep_waves(lds)) {
-    case 4: return sweep_nw<4>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
-    case 8: return sweep_nw<8>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
-    default: return sweep_nw<16>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st);
+    case 4: return sweep_nw<4>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
+    case 8: return sweep_nw<8>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
+    default: return sweep_nw<16>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
     }
 }
 
@@ -1301,29 +1379,37 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
 // With grid == 0 only the kernel's LDS limit is raised (outside any graph capture).
 hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
-                              int waves, int grid, int maxWx, unsigned long long *work, hipStream_t st) {
+                              int waves, int grid, int maxWx, int maxK, unsigned long long *work,
+                              hipStream_t st) {
     int rmq = 0;
     const size_t lds = sweep_lds_launch(maxWx, f64, rmq);
-#define TVS_BATCH_GO(TZ, NW, RCP, TAB)                                                                  \
+    // the same choice as launch_sweep's, so a tile's rows take the same steps in either path
+    const bool slide = f64 && rmq && maxK <= SLIDE_MAX_K;
+#define TVS_BATCH_GO(TZ, NW, RCP, SL, TAB)                                                              \
     do {                                                                                                \
-        auto f = k_sweep_batch<TZ, NW, RCP>;                                                            \
+        auto f = k_sweep_batch<TZ, NW, RCP, SL>;                                                        \
         if (grid == 0) return set_lds(f, lds);                                                          \
         f<<<grid, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work, rmq);                  \
     } while (0)
+#define TVS_BATCH_NW(NW)                                                                                \
+    do {                                                                                                \
+        if (f64 && slide) {                                                                             \
+            if (rcp) TVS_BATCH_GO(double, NW, true, true, tab64);                                       \
+            else TVS_BATCH_GO(double, NW, false, true, tab64);                                          \
+        } else if (f64) {                                                                               \
+            if (rcp) TVS_BATCH_GO(double, NW, true, false, tab64);                                      \
+            else TVS_BATCH_GO(double, NW, false, false, tab64);                                         \
+        } else {                                                                                        \
+            if (rcp) TVS_BATCH_GO(float, NW, true, false, tab32);                                       \
+            else TVS_BATCH_GO(float, NW, false, false, tab32);                                          \
+        }                                                                                               \
+    } while (0)
     switch (waves) {
-    case 2:
-        if (f64) { if (rcp) TVS_BATCH_GO(double, 2, true, tab64); else TVS_BATCH_GO(double, 2, false, tab64); }
-        else { if (rcp) TVS_BATCH_GO(float, 2, true, tab32); else TVS_BATCH_GO(float, 2, false, tab32); }
-        break;
-    case 8:
-        if (f64) { if (rcp) TVS_BATCH_GO(double, 8, true, tab64); else TVS_BATCH_GO(double, 8, false, tab64); }
-        else { if (rcp) TVS_BATCH_GO(float, 8, true, tab32); else TVS_BATCH_GO(float, 8, false, tab32); }
-        break;
-    default:
-        if (f64) { if (rcp) TVS_BATCH_GO(double, 4, true, tab64); else TVS_BATCH_GO(double, 4, false, tab64); }
-        else { if (rcp) TVS_BATCH_GO(float, 4, true, tab32); else TVS_BATCH_GO(float, 4, false, tab32); }
-        break;
+    case 2: TVS_BATCH_NW(2); break;
+    case 8: TVS_BATCH_NW(8); break;
+    default: TVS_BATCH_NW(4); break;
     }
+#undef TVS_BATCH_NW
 #undef TVS_BATCH_GO
     return hipGetLastError();
 }
