@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <atomic>
+#include <climits>
 #include <mutex>
 #include <unordered_map>
 #include <math.h>
@@ -401,9 +402,10 @@ struct RingAcc {
 // every remaining slope is at most max(slope(RN(zs - h), m), 0) (a negative difference gives a
 // negative slope). When that bound is <= the lane's horizon, no later target passes the strict
 // test, the clipped last ring included, and the ring sums are those of the full walk.
-// With SLIDE the skip test reads the sliding maxima `slide` instead of the table's level 1, and
-// the launch keeps every exit range within the table (there is no `bnd`).
-template <typename Tz, int DIR, bool RCP, bool PRUNE, bool SLIDE>
+// With SLIDE (the number of table levels, 0 without) the skip test reads the sliding maxima `slide`
+// instead of the table's level 1, and the launch keeps every exit range within the table (there is
+// no `bnd`).
+template <typename Tz, int DIR, bool RCP, bool PRUNE, int SLIDE>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
                                               const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
@@ -413,9 +415,10 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     // holds back the early exit (its sums are discarded)
     Tz mx = (PRUNE && !live) ? -neg_inf<Tz>() : neg_inf<Tz>();
     const int mfull = (mb == K) ? K - 1 : mb;
-    // maximum over blocks lo..hi (1 <= hi - lo + 1 <= 64) from the range table
+    constexpr int NLEV = SLIDE ? SLIDE : RMQ_LEVELS;
+    // maximum over blocks lo..hi (1 <= hi - lo + 1 <= 2^NLEV) from the range table
     auto range_max = [&](int lo, int hi) -> Tz {
-        const int l = min(31 - __builtin_clz(hi - lo + 1), RMQ_LEVELS - 1);
+        const int l = min(31 - __builtin_clz(hi - lo + 1), NLEV - 1);
         const float *T = rmq + l * nb;
         float zf;  // the table holds no NaN: a plain max, without canonicalising its inputs
         asm("v_max_f32 %0, %1, %2" : "=v"(zf) : "v"(T[lo]), "v"(T[hi - (1 << l) + 1]));
@@ -439,9 +442,9 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         const int lo = DIR > 0 ? bnear : bfar, hi = DIR > 0 ? bfar : bnear;
         const int len = hi - lo + 1;
         // (with SLIDE a range past the table bounds nothing: +inf, and the wavefront walks on)
-        const Tz zs = (rmq && len >= 1 && len <= 2 << (RMQ_LEVELS - 1)) ? range_max(lo, hi)
-                      : SLIDE                                              ? -neg_inf<Tz>()
-                                                                           : bnd[bnear];
+        const Tz zs = (rmq && len >= 1 && len <= 1 << NLEV) ? range_max(lo, hi)
+                      : SLIDE                                ? -neg_inf<Tz>()
+                                                             : bnd[bnear];
         return bounded_by(zs, mm, mb);
     };
     // the wavefront skips steps mm .. mm + 31: none of their targets can be visible on any lane.
@@ -453,7 +456,7 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     auto block_hidden = [&](int mm) -> bool {
         const int first = DIR > 0 ? q + mm : q - mm - 31;  // the lane's lowest target position
         float zf;
-        if constexpr (SLIDE) {
+        if constexpr (SLIDE != 0) {
             zf = slide[min(max(first >> 3, 0), 4 * nb - 1)];
         } else {
             const int b = min(max(first >> 5, 0), nb - 1);
@@ -552,10 +555,11 @@ __device__ void sliding_max40(const Tz *z, int nb, float *slide) {
 // Per-block elevation maxima of a row of nt samples (followed by -inf sentinels): pre[b] is the
 // maximum over blocks 0..b, suf[b] over blocks b..nb-1, each scanned by one wavefront with the
 // wavefront prefix-max. With `rmq`, level l of the table holds at rmq[l nb + b] the maximum over
-// blocks b .. min(b + 2^l, nb) - 1, rounded up to float. With SLIDE the table and the sliding
-// maxima of 40 samples are built instead (no suf and pre).
-template <typename Tz, bool SLIDE>
+// blocks b .. min(b + 2^l, nb) - 1, rounded up to float. With SLIDE the table (SLIDE levels) and
+// the sliding maxima of 40 samples are built instead (no suf and pre).
+template <typename Tz, int SLIDE>
 __device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq, float *slide) {
+    constexpr int NLEV = SLIDE ? SLIDE : RMQ_LEVELS;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         Tz m = z[32 * b];
 #pragma unroll
@@ -566,10 +570,10 @@ __device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq, 
         }
         if (rmq) rmq[b] = ru_float(m);
     }
-    if constexpr (SLIDE) sliding_max40(z, nb, slide);  // its barriers also order the table's first level
+    if constexpr (SLIDE != 0) sliding_max40(z, nb, slide);  // its barriers also order the table's first level
     __syncthreads();
     if (rmq) {
-        for (int l = 1; l < RMQ_LEVELS; ++l) {
+        for (int l = 1; l < NLEV; ++l) {
             const float *src = rmq + (l - 1) * nb;
             float *dst = rmq + l * nb;
             const int half = 1 << (l - 1);
@@ -630,19 +634,19 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int
 // sides, room for the early exit's block maxima after them) and stores U | e << 30 of POV q at
 // dst[q]. Returns the evaluations this lane carried out when `count` is set. After the row lie
 // the suffix and prefix block maxima, then (use_rmq) the range-maximum table; with SLIDE the
-// table, then the sliding maxima of 40 samples at every 8th position.
-template <typename Tz, int NW, bool RCP, bool PRUNE, bool SLIDE = false>
+// table of SLIDE levels, then the sliding maxima of 40 samples at every 8th position.
+template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE = 0>
 __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                               const typename Tab<Tz>::type *__restrict__ tab,
                                               uint32_t *__restrict__ dst, bool count, bool use_rmq) {
     const int nb = (nt + 31) >> 5;
     Tz *suf = nullptr, *pre = nullptr;
     float *rmq, *slide = nullptr;
-    if constexpr (SLIDE) {
+    if constexpr (SLIDE != 0) {
         // launches with SLIDE set use_rmq; a pointer the compiler cannot prove non-null keeps the
         // block loop's ring sums in place (proven, its loop copies them on every block)
         rmq = use_rmq ? reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) : nullptr;
-        slide = reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) + RMQ_LEVELS * nb;
+        slide = reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) + SLIDE * nb;
     } else {
         suf = row + nt + 2 * TVS_SWEEP_PAD;
         pre = suf + nb;
@@ -690,7 +694,7 @@ __device__ __forceinline__ void add_work(unsigned long long *work, unsigned long
     if (threadIdx.x == 0) atomicAdd(&work[slot & 63], wg_work);
 }
 
-template <typename Tz, int NW, bool RCP, bool PRUNE, bool SLIDE = false>
+template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE = 0>
 __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
                                                    const typename Tab<Tz>::type *__restrict__ tab,
@@ -756,7 +760,7 @@ template <> __device__ __forceinline__ double h0_of<double>(const BatchEnt &e) {
 // Persistent sweep over every (tile, sector, skewed row) item of a batch chunk: each workgroup
 // takes the next item from a device counter until the list is exhausted (every workgroup
 // reaches the end, the counter only grows), gathers the row from its tile's DEM and sweeps it.
-template <typename Tz, int NW, bool RCP, bool SLIDE = false>
+template <typename Tz, int NW, bool RCP, int SLIDE = 0>
 __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restrict__ ent,
                                                          const uint32_t *__restrict__ items, int nitems,
                                                          unsigned int *__restrict__ counter, uint32_t *__restrict__ V,
@@ -1235,17 +1239,21 @@ size_t sweep_lds_bytes(int maxWx, bool f64) {
     return (size_t)(maxWx + 2 * TVS_SWEEP_PAD + 2 * ((maxWx + 31) / 32)) * (f64 ? sizeof(double) : sizeof(float));
 }
 
-// Largest step count (K capped at the row length) for which every early-exit range of a
+// Largest step counts (K capped at the row length) for which every early-exit range of a
 // wavefront, from the block of its nearest remaining target to the farthest block its lanes
-// reach, spans at most the 64 blocks the range-maximum table covers: fewer than (K + 62) / 32 + 2
-// blocks. Launches within it may use the sliding maxima, which need no suffix or prefix maxima.
-constexpr int SLIDE_MAX_K = 1900;
+// reach, spans at most the 64 (with one more level, 128) blocks the range-maximum table covers:
+// fewer than (K + 62) / 32 + 2 blocks. Launches within them may use the sliding maxima, which need
+// no suffix or prefix maxima.
+constexpr int SLIDE_MAX_K = 1900, SLIDE_MAX_K_LONG = 3900;
 
 // The sweep's LDS with the early exit's range-maximum table when it fits the workgroup limit
-// (rmq = 1), else without it (rmq = 0).
-static size_t sweep_lds_launch(int maxWx, bool f64, int &rmq) {
+// (rmq = 1), else without it (rmq = 0). `slide` is the sweep's SLIDE for double rows whose step
+// counts (at most maxK) allow it: RMQ_LEVELS in the LDS of the suffix and prefix maxima (the same
+// bytes), RMQ_LEVELS + 1 with 4 B more per block when that keeps the workgroups per CU; else 0.
+static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &slide) {
+    const size_t nbx = (maxWx + 31) / 32;
     const size_t base = sweep_lds_bytes(maxWx, f64);
-    const size_t full = base + (size_t)RMQ_LEVELS * ((maxWx + 31) / 32) * sizeof(float);
+    const size_t full = base + (size_t)RMQ_LEVELS * nbx * sizeof(float);
     // the device's limit, queried once per device (the first launch on it is not captured)
     static std::atomic<int> caps[64];
     int dev = 0, cap = 0;
@@ -1260,6 +1268,15 @@ static size_t sweep_lds_launch(int maxWx, bool f64, int &rmq) {
         }
     }
     rmq = full + 64 <= (size_t)cap ? 1 : 0;  // + the kernels' static LDS
+    slide = 0;
+    if (f64 && rmq && maxK <= SLIDE_MAX_K) slide = RMQ_LEVELS;
+    if (f64 && rmq && maxK > SLIDE_MAX_K && maxK <= SLIDE_MAX_K_LONG) {
+        const size_t deep = full + nbx * sizeof(float), per_cu = 160 * 1024;
+        if (deep + 64 <= (size_t)cap && per_cu / (deep + 64) == per_cu / (full + 64)) {
+            slide = RMQ_LEVELS + 1;
+            return deep;
+        }
+    }
     return rmq ? full : base;
 }
 
@@ -1313,9 +1330,14 @@ static hipError_t sweep_go(void (*f)(ChunkArgs, const Tz *, uint32_t *, const ty
 template <int NW>
 static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void *skw, uint32_t *V,
                            const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
-                           bool slide, unsigned long long *work, hipStream_t st) {
-    if (f64 && slide) {
-        auto f = rcp ? k_sweep<double, NW, true, true, true> : k_sweep<double, NW, false, true, true>;
+                           int slide, unsigned long long *work, hipStream_t st) {
+    constexpr int S6 = RMQ_LEVELS, S7 = RMQ_LEVELS + 1;
+    if (f64 && prune && !scan && slide == S6) {
+        auto f = rcp ? k_sweep<double, NW, true, true, S6> : k_sweep<double, NW, false, true, S6>;
+        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+    }
+    if (f64 && prune && !scan && slide == S7) {
+        auto f = rcp ? k_sweep<double, NW, true, true, S7> : k_sweep<double, NW, false, true, S7>;
         return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
     }
     if (f64) {
@@ -1346,11 +1368,10 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
                         unsigned long long *work, hipStream_t st) {
     const dim3 grid(maxRows, a.nsec);
     ChunkArgs b = a;
-    const size_t lds = sweep_lds_launch(maxWx, f64, b.rmq);
-    // the sliding maxima take the LDS of the suffix and prefix maxima of double rows
-    int maxK = 0;
+    int maxK = 0, slide = 0;
     for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
-    const bool slide = f64 && prune && !scan && b.rmq && maxK <= SLIDE_MAX_K;
+    // without the early exit or in the lane-per-target variant no sliding maxima
+    const size_t lds = sweep_lds_launch(maxWx, f64, prune && !scan ? maxK : INT_MAX, b.rmq, slide);
     switch (sweep_waves(lds)) {
     case 4: return sweep_nw<4>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
     case 8: return sweep_nw<8>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
@@ -1381,10 +1402,9 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, int maxK, unsigned long long *work,
                               hipStream_t st) {
-    int rmq = 0;
-    const size_t lds = sweep_lds_launch(maxWx, f64, rmq);
     // the same choice as launch_sweep's, so a tile's rows take the same steps in either path
-    const bool slide = f64 && rmq && maxK <= SLIDE_MAX_K;
+    int rmq = 0, slide = 0;
+    const size_t lds = sweep_lds_launch(maxWx, f64, maxK, rmq, slide);
 #define TVS_BATCH_GO(TZ, NW, RCP, SL, TAB)                                                              \
     do {                                                                                                \
         auto f = k_sweep_batch<TZ, NW, RCP, SL>;                                                        \
@@ -1393,15 +1413,18 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
     } while (0)
 #define TVS_BATCH_NW(NW)                                                                                \
     do {                                                                                                \
-        if (f64 && slide) {                                                                             \
-            if (rcp) TVS_BATCH_GO(double, NW, true, true, tab64);                                       \
-            else TVS_BATCH_GO(double, NW, false, true, tab64);                                          \
+        if (f64 && slide == RMQ_LEVELS) {                                                               \
+            if (rcp) TVS_BATCH_GO(double, NW, true, RMQ_LEVELS, tab64);                                 \
+            else TVS_BATCH_GO(double, NW, false, RMQ_LEVELS, tab64);                                    \
+        } else if (f64 && slide == RMQ_LEVELS + 1) {                                                    \
+            if (rcp) TVS_BATCH_GO(double, NW, true, RMQ_LEVELS + 1, tab64);                             \
+            else TVS_BATCH_GO(double, NW, false, RMQ_LEVELS + 1, tab64);                                \
         } else if (f64) {                                                                               \
-            if (rcp) TVS_BATCH_GO(double, NW, true, false, tab64);                                      \
-            else TVS_BATCH_GO(double, NW, false, false, tab64);                                         \
+            if (rcp) TVS_BATCH_GO(double, NW, true, 0, tab64);                                          \
+            else TVS_BATCH_GO(double, NW, false, 0, tab64);                                             \
         } else {                                                                                        \
-            if (rcp) TVS_BATCH_GO(float, NW, true, false, tab32);                                       \
-            else TVS_BATCH_GO(float, NW, false, false, tab32);                                          \
+            if (rcp) TVS_BATCH_GO(float, NW, true, 0, tab32);                                           \
+            else TVS_BATCH_GO(float, NW, false, 0, tab32);                                              \
         }                                                                                               \
     } while (0)
     switch (waves) {

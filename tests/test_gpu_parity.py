@@ -216,9 +216,10 @@ def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
 # (ranges beyond the range table's 64 blocks fall back to the row-end maxima), and rows of 18000
 # doubles or 32767 floats, whose LDS leaves no room for the range table (early exit on the row-end
 # maxima alone, no block skipping). Two sectors keep the skewed arrays small (tan s' = 0).
-# unbounded steps; 1900 steps (the most the sliding maxima of the skip test take: exit ranges up to
-# 61 blocks, all within the range table); 1950 steps (the block-pair skip test); 3800 steps (exit
-# ranges past the table: the accumulated maxima); rows beyond the table's LDS; float rows
+# unbounded steps (the block-pair skip test, exit ranges past the table: the accumulated maxima);
+# 1900 steps (the most the sliding maxima take with the 6-level table: exit ranges up to 61 blocks);
+# 1950 and 3800 steps (the 7-level table: exit ranges up to 63 and 122 blocks); rows beyond the
+# table's LDS; float rows
 LONG_ROWS = [(5, 4000, INF, 0, P_DEFAULT), (5, 4000, 19000.0, 0, P_DEFAULT), (5, 4000, 19500.0, 0, P_DEFAULT),
              (5, 4000, 38000.0, 0, P_DEFAULT), (2, 18000, 2500.0, 0, P_DEFAULT), (3, 32767, 3000.0, F32, P_F32)]
 
