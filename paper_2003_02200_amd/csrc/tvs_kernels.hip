@@ -1247,9 +1247,10 @@ size_t sweep_lds_bytes(int maxWx, bool f64) {
 constexpr int SLIDE_MAX_K = 1900, SLIDE_MAX_K_LONG = 3900;
 
 // The sweep's LDS with the early exit's range-maximum table when it fits the workgroup limit
-// (rmq = 1), else without it (rmq = 0). `slide` is the sweep's SLIDE for double rows whose step
-// counts (at most maxK) allow it: RMQ_LEVELS in the LDS of the suffix and prefix maxima (the same
-// bytes), RMQ_LEVELS + 1 with 4 B more per block when that keeps the workgroups per CU; else 0.
+// (rmq = 1), else without it (rmq = 0). `slide` is the sweep's SLIDE for rows whose step counts (at
+// most maxK) allow it: RMQ_LEVELS, or RMQ_LEVELS + 1 for longer lines of sight, when the row with
+// those tables still fits as many workgroups per CU (up to the 8 four-wave workgroups a CU holds);
+// else 0. For double rows the 6-level tables take the bytes of the suffix and prefix maxima.
 static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &slide) {
     const size_t nbx = (maxWx + 31) / 32;
     const size_t base = sweep_lds_bytes(maxWx, f64);
@@ -1269,12 +1270,14 @@ static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &sli
     }
     rmq = full + 64 <= (size_t)cap ? 1 : 0;  // + the kernels' static LDS
     slide = 0;
-    if (f64 && rmq && maxK <= SLIDE_MAX_K) slide = RMQ_LEVELS;
-    if (f64 && rmq && maxK > SLIDE_MAX_K && maxK <= SLIDE_MAX_K_LONG) {
-        const size_t deep = full + nbx * sizeof(float), per_cu = 160 * 1024;
-        if (deep + 64 <= (size_t)cap && per_cu / (deep + 64) == per_cu / (full + 64)) {
-            slide = RMQ_LEVELS + 1;
-            return deep;
+    if (rmq && maxK <= SLIDE_MAX_K_LONG) {
+        const int lev = maxK <= SLIDE_MAX_K ? RMQ_LEVELS : RMQ_LEVELS + 1;
+        const size_t bytes = (size_t)(maxWx + 2 * TVS_SWEEP_PAD) * (f64 ? sizeof(double) : sizeof(float)) +
+                             (size_t)(lev + 4) * nbx * sizeof(float);
+        auto resident = [](size_t b) { return std::min<size_t>((160 * 1024) / (b + 64), 8); };
+        if (bytes + 64 <= (size_t)cap && resident(bytes) >= resident(full)) {
+            slide = lev;
+            return bytes;
         }
     }
     return rmq ? full : base;
@@ -1332,13 +1335,15 @@ static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void
                            const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
                            int slide, unsigned long long *work, hipStream_t st) {
     constexpr int S6 = RMQ_LEVELS, S7 = RMQ_LEVELS + 1;
-    if (f64 && prune && !scan && slide == S6) {
-        auto f = rcp ? k_sweep<double, NW, true, true, S6> : k_sweep<double, NW, false, true, S6>;
-        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
-    }
-    if (f64 && prune && !scan && slide == S7) {
-        auto f = rcp ? k_sweep<double, NW, true, true, S7> : k_sweep<double, NW, false, true, S7>;
-        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+    if (prune && !scan && (slide == S6 || slide == S7)) {
+        if (f64) {
+            auto f = slide == S6 ? (rcp ? k_sweep<double, NW, true, true, S6> : k_sweep<double, NW, false, true, S6>)
+                                 : (rcp ? k_sweep<double, NW, true, true, S7> : k_sweep<double, NW, false, true, S7>);
+            return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+        }
+        auto f = slide == S6 ? (rcp ? k_sweep<float, NW, true, true, S6> : k_sweep<float, NW, false, true, S6>)
+                             : (rcp ? k_sweep<float, NW, true, true, S7> : k_sweep<float, NW, false, true, S7>);
+        return sweep_go<float>(f, NW, grid, lds, st, a, skw, V, tab32, work);
     }
     if (f64) {
         auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
@@ -1422,6 +1427,12 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
         } else if (f64) {                                                                               \
             if (rcp) TVS_BATCH_GO(double, NW, true, 0, tab64);                                          \
             else TVS_BATCH_GO(double, NW, false, 0, tab64);                                             \
+        } else if (slide == RMQ_LEVELS) {                                                               \
+            if (rcp) TVS_BATCH_GO(float, NW, true, RMQ_LEVELS, tab32);                                  \
+            else TVS_BATCH_GO(float, NW, false, RMQ_LEVELS, tab32);                                     \
+        } else if (slide == RMQ_LEVELS + 1) {                                                           \
+            if (rcp) TVS_BATCH_GO(float, NW, true, RMQ_LEVELS + 1, tab32);                              \
+            else TVS_BATCH_GO(float, NW, false, RMQ_LEVELS + 1, tab32);                                 \
         } else {                                                                                        \
             if (rcp) TVS_BATCH_GO(float, NW, true, 0, tab32);                                           \
             else TVS_BATCH_GO(float, NW, false, 0, tab32);                                              \
