@@ -14,8 +14,9 @@
 //               with the lane's running maximum and adds the ring weight 2m+1 when visible.
 //               The ring sums are integers (Alg. 8's dd^2 - open_dd^2 telescopes to a sum of
 //               2m+1 over visible samples), so they are kept exactly in u32. Exact bounds from
-//               per-block elevation maxima skip 32-step blocks no lane can see into and stop a
-//               wavefront when nothing further can be visible (same results as the full walk).
+//               elevation maxima (per block, and sliding over 40 samples where the LDS allows)
+//               skip 32-step blocks no lane can see into and stop a wavefront when nothing
+//               further can be visible (same results as the full walk).
 //   k_backproj  skwVS -> VS (Alg. 9): each DEM cell blends the two skewed samples around it,
 //               scales by the half-sector ring area (Alg. 1's pi/ns, Alg. 7's 1/cos^2) and
 //               accumulates over sectors in double.
