@@ -437,10 +437,11 @@ def test_workload_2000_sampled(tvs, orc):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(full.cpu().numpy(), g)
     del full
-    # the exact bounds must keep doing their work: on this workload the sweep carries out 41.7 % of
-    # the evaluations (a guard against the block skip or the early exit silently switching off)
+    # the exact bounds must keep doing their work: on this workload the sweep carries out 39.5 % of
+    # the evaluations with the skip test on sliding maxima, 41.7 % on block pairs (a guard against
+    # the sliding maxima, the block skip or the early exit silently switching off)
     _, st = tvs.total_viewshed(d, *args, flags=tvs.FLAG_COUNT_EVALS, stats=True)
-    assert st.sweep_evals_done < 0.45 * st.los_evals, st.sweep_evals_done / st.los_evals
+    assert st.sweep_evals_done < 0.405 * st.los_evals, st.sweep_evals_done / st.los_evals
     R = w["max_dist"]
     assert np.all(np.isfinite(g)) and np.all(g > 0) and np.all(g <= math.pi * R * R * (1 + 1e-12))
     rng = np.random.default_rng(2000)
