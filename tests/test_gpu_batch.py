@@ -166,3 +166,32 @@ def test_batch_autotune(tvs):
     assert b2.info().tuned == 1 and b2.info().waves_per_group == inf.waves_per_group
     b.close()
     b2.close()
+
+
+def test_batch_long_lines_of_sight(tvs):
+    """Tiles whose lines of sight reach up to 2000 steps: the batch and each tile alone take the
+    sliding maxima with the deeper range table; maps equal the full walk's, counts equal the
+    single-tile counts."""
+    import torch
+
+    n = 8
+    tiles = [(3, 2100, 10.0, 1.5, 20000.0), (4, 2050, 10.0, 5.0, 19500.0), (2, 1000, 10.0, 1.5, 9000.0)]
+    rng = np.random.default_rng(43)
+    dems = [torch.from_numpy((800.0 + rng.normal(0.0, 3.0, (H, W)).cumsum(axis=1)).astype(np.float32)).cuda()
+            for (H, W, *_r) in tiles]
+    outs = _outs(tiles, 0.0)
+    note("batch with lines of sight up to 2000 steps")
+    b = tvs.Batch([(dems[x], outs[x], *tiles[x][2:]) for x in range(len(tiles))], n, flags=tvs.FLAG_COUNT_EVALS)
+    b.run()
+    torch.cuda.synchronize()
+    done = 0
+    for x, (H, W, dx, h0, R) in enumerate(tiles):
+        ref, st = tvs.total_viewshed(dems[x], dx, h0, n, R, flags=tvs.FLAG_COUNT_EVALS, stats=True)
+        full = tvs.total_viewshed(dems[x], dx, h0, n, R, flags=tvs.FLAG_NO_PRUNE)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(ref.cpu().numpy(), full.cpu().numpy())
+        np.testing.assert_allclose(outs[x].cpu().numpy(), ref.cpu().numpy(), rtol=1e-13, atol=0)
+        assert 0 < st.sweep_evals_done < st.los_evals
+        done += st.sweep_evals_done
+    assert b.info().sweep_evals_done == done
+    b.close()
