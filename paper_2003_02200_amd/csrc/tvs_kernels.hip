@@ -519,11 +519,12 @@ __device__ __forceinline__ float ru_float(float x) { return x; }
 
 // Maxima of the row's samples 8k .. 8k + 39 (sentinels past the row end), rounded up to float, at
 // slide[k] for k < 4 nb. A wavefront reads 64 consecutive samples; three row shifts leave the
-// maximum of each group of 8 lanes in its last lane. Then each entry takes the maximum of itself
-// and the next four, in tiles of one workgroup: a tile reads before any of its entries is
-// written, and later tiles read only entries at or beyond their own.
+// maximum of each group of 8 lanes in its last lane. With `blk` the block maxima (rounded up) come
+// from these groups, four per block. Then each entry takes the maximum of itself and the next
+// four, in tiles of one workgroup: a tile reads before any of its entries is written, and later
+// tiles read only entries at or beyond their own.
 template <typename Tz>
-__device__ void sliding_max40(const Tz *z, int nb, float *slide) {
+__device__ void sliding_max40(const Tz *z, int nb, float *slide, float *blk) {
     const int lane = threadIdx.x & 63;
     const int nw = blockDim.x >> 6;
     const int n8 = nb << 2;
@@ -538,6 +539,11 @@ __device__ void sliding_max40(const Tz *z, int nb, float *slide) {
         if ((lane & 7) == 7 && k < n8) slide[k] = ru_float(x);
     }
     __syncthreads();
+    if (blk) {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x)
+            blk[b] = fmaxf(fmaxf(slide[4 * b], slide[4 * b + 1]), fmaxf(slide[4 * b + 2], slide[4 * b + 3]));
+        __syncthreads();
+    }
     for (int t0 = 0; t0 < n8; t0 += blockDim.x) {
         const int k = t0 + threadIdx.x;
         float v = neg_inf<float>();
@@ -561,17 +567,18 @@ __device__ void sliding_max40(const Tz *z, int nb, float *slide) {
 template <typename Tz, int SLIDE>
 __device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq, float *slide) {
     constexpr int NLEV = SLIDE ? SLIDE : RMQ_LEVELS;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
-        Tz m = z[32 * b];
+    if constexpr (SLIDE != 0) {
+        sliding_max40(z, nb, slide, rmq);  // the table's first level from its groups of 8
+    } else {
+        for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+            Tz m = z[32 * b];
 #pragma unroll
-        for (int i = 1; i < 32; ++i) m = vmax(m, z[32 * b + i]);
-        if constexpr (!SLIDE) {
+            for (int i = 1; i < 32; ++i) m = vmax(m, z[32 * b + i]);
             suf[b] = m;
             pre[b] = m;
+            if (rmq) rmq[b] = ru_float(m);
         }
-        if (rmq) rmq[b] = ru_float(m);
     }
-    if constexpr (SLIDE != 0) sliding_max40(z, nb, slide);  // its barriers also order the table's first level
     __syncthreads();
     if (rmq) {
         for (int l = 1; l < NLEV; ++l) {
