@@ -219,9 +219,10 @@ def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
 # unbounded steps (the block-pair skip test, exit ranges past the table: the accumulated maxima);
 # 1900 steps (the most the sliding maxima take with the 6-level table: exit ranges up to 61 blocks);
 # 1950 and 3800 steps (the 7-level table: exit ranges up to 63 and 122 blocks); rows beyond the
-# table's LDS; float rows
+# table's LDS; float rows with the 7-level table and beyond the table's LDS
 LONG_ROWS = [(5, 4000, INF, 0, P_DEFAULT), (5, 4000, 19000.0, 0, P_DEFAULT), (5, 4000, 19500.0, 0, P_DEFAULT),
-             (5, 4000, 38000.0, 0, P_DEFAULT), (2, 18000, 2500.0, 0, P_DEFAULT), (3, 32767, 3000.0, F32, P_F32)]
+             (5, 4000, 38000.0, 0, P_DEFAULT), (2, 18000, 2500.0, 0, P_DEFAULT), (5, 4000, 19500.0, F32, P_F32),
+             (3, 32767, 3000.0, F32, P_F32)]
 
 
 @pytest.mark.parametrize("H,W,R,flags,prec", LONG_ROWS)
