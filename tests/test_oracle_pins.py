@@ -549,6 +549,22 @@ def test_double_reciprocal_decisions_match_quotient(orc):
     assert pairs > 20000
 
 
+def test_double_reciprocal_decisions_match_quotient_whole_workload(orc):
+    """The same on every one of the 180 sectors of the 128x128 workload (seed 1, 0-1500 m, 10 m,
+    1.5 m, max distance 1280 m): 2.97e6 POV-sector pairs, not one decision differs."""
+    from synth import WORKLOADS, workload_dem
+
+    w = WORKLOADS["tvs128"]
+    dem = workload_dem("tvs128")
+    pairs = 0
+    for k in range(w["n_sectors"]):
+        a = orc.sector_V(dem, w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"], k, prec=64)
+        b = orc.sector_V(dem, w["spacing"], w["obs_height"], w["n_sectors"], w["max_dist"], k, prec=65)
+        pairs += int(a["valid"].astype(bool).sum())
+        assert np.array_equal(a["U"], b["U"]) and np.array_equal(a["e"], b["e"]), f"sector {k}"
+    assert pairs == 2971472
+
+
 # ------------------------------------------------------------------ singular mask and multiple viewshed
 
 @pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 12, 180])
