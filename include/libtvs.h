@@ -174,6 +174,25 @@ int tvs_multiple_viewshed(const float *d_dem, int32_t rows, int32_t cols, double
                           int32_t npov, uint32_t flags, uint32_t *d_count, double *d_areas,
                           void *hip_stream);
 
+/* ---- Allocation-free total viewshed --------------------------------------------------------
+ * For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. tvs_total_viewshed_async without any allocation: every
+ * device buffer of the call (reciprocal tables, skewed elevation and viewshed buffers) is carved
+ * from a static device array of TVS_NOALLOC_SCRATCH_BYTES that the library holds on each device it
+ * runs on until the process ends (its address is looked up on a device's first call). The skewed
+ * buffers take the compacted layout (TVS_FLAG_COMPACT) and the sectors are processed in groups
+ * that fit the array; the map is the same as tvs_total_viewshed_async's, bit for bit.
+ * Limit: one sector's skewed buffers, about 12 * (H_x + 1) * P bytes (H_x the sector's rows in its
+ * 0..45 deg frame, P = max(rows, cols) rounded up to 64), must fit the array with the tables;
+ * larger grids return TVS_ERANGE before any work is enqueued (sides up to about 4,700).
+ * Calls on one device share the array: calls whose work overlaps on a device (other streams,
+ * other host threads) race and must be serialised by the caller. The call itself allocates no
+ * device memory, frees none and calls no allocating library routine. */
+#define TVS_NOALLOC_SCRATCH_BYTES (256u << 20)
+int tvs_total_viewshed_noalloc(const float *d_dem, int32_t rows, int32_t cols, double spacing,
+                               double obs_height, int32_t n_sectors, double max_dist, double *d_out,
+                               void *hip_stream);
+
 /* ---- Batches of independent tiles (uneven sizes) -------------------------------------------
  * Every tile is an independent total viewshed (tvs_total_viewshed_async semantics) with its own
  * size, spacing, observer height and max distance; all tiles share n_sectors. */

@@ -17,7 +17,7 @@ __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
     "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "FLAG_COMPACT", "Stats", "Batch", "BatchInfo",
-    "total_viewshed_tiles", "Server", "multiple_viewshed", "singular_mask",
+    "total_viewshed_tiles", "Server", "multiple_viewshed", "singular_mask", "total_viewshed_noalloc",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -129,6 +129,7 @@ def lib():
         L.tvs_server_destroy.argtypes = [vp]
         L.tvs_multiple_viewshed.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp, i32, u32, vp, vp, vp]
         L.tvs_los_evals.argtypes = [i32, i32, f64, i32, f64, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.tvs_total_viewshed_noalloc.argtypes = [vp, i32, i32, f64, f64, i32, f64, vp, vp]
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
                      "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals",
@@ -136,7 +137,7 @@ def lib():
                      "tvs_total_viewshed_tiles", "tvs_server_create", "tvs_server_add_grid",
                      "tvs_server_submit_total", "tvs_server_submit_singular", "tvs_server_wait",
                      "tvs_server_copy_map", "tvs_server_release", "tvs_server_get_stats", "tvs_server_destroy",
-                     "tvs_multiple_viewshed"):
+                     "tvs_multiple_viewshed", "tvs_total_viewshed_noalloc"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -211,6 +212,28 @@ def total_viewshed(dem, spacing: float, obs_height: float, n_sectors: int, max_d
     out = np.empty((H, W), np.float64)
     _check(L.tvs_total_viewshed(a.ctypes.data_as(vp), H, W, spacing, obs_height, n_sectors, max_dist,
                                 out.ctypes.data_as(vp)))
+    return out
+
+
+def total_viewshed_noalloc(dem, spacing: float, obs_height: float, n_sectors: int, max_dist: float = math.inf,
+                           out=None, stream=None):
+    """tvs_total_viewshed_noalloc: the total viewshed of a device grid (CUDA float32 tensor) into
+    ``out`` (a float64 tensor of the grid's shape on the same device; allocated here when None),
+    with no device allocation inside the library call. Ordered on ``stream`` or the current stream."""
+    import torch
+
+    if not (_is_torch_cuda(dem) and dem.dtype == torch.float32 and dem.dim() == 2):
+        raise ValueError("dem must be a 2-D float32 CUDA tensor")
+    d = dem.contiguous()
+    H, W = d.shape
+    if out is None:
+        out = torch.empty((H, W), dtype=torch.float64, device=d.device)
+    if not (_is_torch_cuda(out) and out.dtype == torch.float64 and tuple(out.shape) == (H, W)
+            and out.is_contiguous() and out.device == d.device):
+        raise ValueError("out must be a contiguous float64 CUDA tensor of the grid's shape on its device")
+    with torch.cuda.device(d.device):
+        _check(lib().tvs_total_viewshed_noalloc(C.c_void_p(d.data_ptr()), H, W, spacing, obs_height, n_sectors,
+                                                max_dist, C.c_void_p(out.data_ptr()), _stream_handle(stream)))
     return out
 
 

@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "../../include/libtvs.h"
@@ -277,9 +278,13 @@ struct Timer {
 
 // The total viewshed on the device: one chunk of sectors at a time, relocation -> sweep ->
 // back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
+// With `fixed` non-null the call takes no device memory of its own: every buffer is carved from the
+// `fixed_bytes` at `fixed` (the allocation-free entry point's static array), the skewed buffers use
+// the compacted layout, and sector chunks are sized to fit; a sector that alone does not fit is
+// rejected with TVS_ERANGE before anything is enqueued.
 int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
               uint32_t flags, tvs_stats *stats, hipStream_t st, int debug_sector, uint32_t *d_debugV,
-              int *debug_pitch, size_t budget = 0) {
+              int *debug_pitch, size_t budget = 0, void *fixed = nullptr, size_t fixed_bytes = 0) {
     const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
@@ -289,7 +294,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     if (count && !stats) return fail(TVS_EINVAL, "TVS_FLAG_COUNT_EVALS needs a stats argument");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
-    pool_keep_memory(dev);
+    if (!fixed) pool_keep_memory(dev);
     const int pitch = pitch_of(H, W);
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
     if (sweep_lds_bytes(std::max(H, W), f64) + 64 > (size_t)lds_limit(dev))  // + the kernels' static LDS
@@ -302,25 +307,38 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     else
         for (int k = 0; k < n; ++k) {
             S.push_back(plan_sector(k, n, H, W, dx, R));
-            if (flags & TVS_FLAG_COMPACT) compact_layout(S.back());
+            if ((flags & TVS_FLAG_COMPACT) || fixed) compact_layout(S.back());
         }
-    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, budget ? budget : scratch_budget());
-    size_t maxChunk = 0;
-    for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
     const int tabN = std::max(H, W);  // entries for m = 1 .. max(H, W)
     const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
     const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
     constexpr int kWorkSlots = 64;  // evaluation counters of the sweep (TVS_FLAG_COUNT_EVALS)
+    // every carved piece is rounded up to 256 bytes: at most 5 pieces besides the skewed buffers
+    const size_t fixedParts = tabBytes + kahanBytes + 256 * 4 + kWorkSlots * 8 + 6 * 256;
+    if (fixed && fixed_bytes <= fixedParts)
+        return fail(TVS_ERANGE, "tables of a %d x %d grid (%zu bytes) exceed the %zu-byte allocation-free scratch",
+                    H, W, fixedParts, fixed_bytes);
+    const size_t chunkBudget = fixed ? fixed_bytes - fixedParts : budget ? budget : scratch_budget();
+    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, chunkBudget);
+    size_t maxChunk = 0;
+    for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
+    if (fixed && maxChunk > chunkBudget)
+        return fail(TVS_ERANGE,
+                    "one sector of a %d x %d grid needs %zu bytes of skewed buffers; the allocation-free scratch "
+                    "holds %zu",
+                    H, W, maxChunk, chunkBudget);
     const size_t total = tabBytes + kahanBytes + 256 * 4 + kWorkSlots * 8 + maxChunk;
 
     Scratch scr;
     scr.st = st;
-    if (hipMallocAsync(&scr.p, total, st) != hipSuccess) {
+    if (fixed) {
+        scr.p = nullptr;  // not owned: nothing to free
+    } else if (hipMallocAsync(&scr.p, total, st) != hipSuccess) {
         (void)hipGetLastError();
         scr.p = nullptr;
         return fail(TVS_ENOMEM, "device scratch of %zu bytes not available", total);
     }
-    char *base = (char *)scr.p;
+    char *base = fixed ? (char *)fixed : (char *)scr.p;
     auto carve = [&](size_t b) {
         char *p = base;
         base += (b + 255) & ~(size_t)255;
@@ -572,7 +590,50 @@ size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t fl
 }  // namespace host
 }  // namespace tvs
 
+// ---------------------------------------------------------------- allocation-free variant
+// Device memory of tvs_total_viewshed_noalloc: one copy of this array per device, allocated when
+// the library's code object is loaded on the device and held until the process ends. In host code
+// the name stands for a host-side symbol, not a device address: host code uses only the address
+// that hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[TVS_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+std::mutex g_noalloc_mu;
+void *g_noalloc_base[64];  // per device: this device's address of `scratch`
+
+// Address of the current device's `scratch`, looked up once per device with that device current.
+int noalloc_base(void **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(TVS_EDEVICE, "device ordinal %d outside 0..63", dev);
+    std::lock_guard<std::mutex> g(g_noalloc_mu);
+    if (!g_noalloc_base[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(TVS_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_noalloc_base[dev] = p;
+    }
+    *out = g_noalloc_base[dev];
+    return TVS_OK;
+}
+
+}  // namespace
+
 extern "C" {
+
+int tvs_total_viewshed_noalloc(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
+                               int32_t n_sectors, double max_dist, double *d_out, void *hip_stream) {
+    g_err[0] = 0;
+    if (!d_dem || !d_out) return fail(TVS_EINVAL, "null dem or out pointer");
+    int rc = check_scalars(rows, cols, spacing, obs_height, n_sectors, max_dist);
+    if (rc) return rc;
+    void *base = nullptr;
+    if ((rc = noalloc_base(&base))) return rc;
+    return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, 0u, nullptr,
+                     (hipStream_t)hip_stream, -1, nullptr, nullptr, 0, base, TVS_NOALLOC_SCRATCH_BYTES);
+}
 
 int tvs_abi_version(void) { return TVS_ABI_VERSION; }
 
