@@ -82,6 +82,11 @@ enum tvs_status {
 #define TVS_FLAG_AUTOTUNE 0x80u   /* batches only: time the candidate launch shapes on a sample of
                                      the batch before building it and keep the fastest for batches
                                      of the same size class (process-wide) */
+#define TVS_FLAG_RELOCATE 0x200u  /* total viewshed: run the relocation as its own kernel that writes every
+                                     sector's skewed elevations (skwDEM) to device memory, and sweep from
+                                     there (Section 4.2's first kernel); by default each sweep workgroup
+                                     gathers its skewed row from the grid with the same interpolation, and no
+                                     skwDEM exists. Same results bit for bit. */
 #define TVS_FLAG_COMPACT 0x100u   /* total viewshed and batches: compacted skewed buffers (Section 3.1,
                                      the second compaction of Figure 4): skewed row t of a base frame
                                      with Hx rows is stored in row t mod (Hx + 1), since rows that far

@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
-    "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "FLAG_COMPACT", "Stats", "Batch", "BatchInfo",
+    "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "FLAG_COMPACT", "FLAG_RELOCATE", "Stats", "Batch", "BatchInfo",
     "total_viewshed_tiles", "Server", "multiple_viewshed", "singular_mask", "total_viewshed_noalloc",
 ]
 
@@ -32,6 +32,7 @@ FLAG_COUNT_EVALS = 0x20
 FLAG_SLOPE_F32 = 0x40
 FLAG_AUTOTUNE = 0x80
 FLAG_COMPACT = 0x100  # skewed row t stored in row t mod (Hx + 1): Hx + 1 rows per sector
+FLAG_RELOCATE = 0x200  # relocation kernel writes skwDEM; the sweep reads it (default: rows gathered from the grid)
 
 _STATUS = {0: "TVS_OK", -1: "TVS_EINVAL", -2: "TVS_ENOMEM", -3: "TVS_EDEVICE", -4: "TVS_ERANGE", -5: "TVS_ETIMEDOUT"}
 

@@ -125,7 +125,7 @@ int check_host_dem(const float *dem, int rows, int cols) {
 
 int check_flags(uint32_t flags, bool accumulation) {
     const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_NO_PRUNE |
-                           TVS_FLAG_SLOPE_F32 |
+                           TVS_FLAG_SLOPE_F32 | TVS_FLAG_RELOCATE |
                            (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS | TVS_FLAG_COMPACT : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
     if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
@@ -276,7 +276,8 @@ struct Timer {
     }
 };
 
-// The total viewshed on the device: one chunk of sectors at a time, relocation -> sweep ->
+// The total viewshed on the device: one chunk of sectors at a time, sweep (each workgroup gathering
+// its skewed row from the grid; with TVS_FLAG_RELOCATE a relocation launch writes skwDEM first) ->
 // back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
 // With `fixed` non-null the call takes no device memory of its own: every buffer is carved from the
 // `fixed_bytes` at `fixed` (the allocation-free entry point's static array), the skewed buffers use
@@ -291,12 +292,14 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const bool rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
     const bool prune = (flags & TVS_FLAG_NO_PRUNE) == 0;
     const bool count = (flags & TVS_FLAG_COUNT_EVALS) != 0;
+    const bool fused = (flags & TVS_FLAG_RELOCATE) == 0;
     if (count && !stats) return fail(TVS_EINVAL, "TVS_FLAG_COUNT_EVALS needs a stats argument");
     int dev = 0;
     HIPCHK(hipGetDevice(&dev));
     if (!fixed) pool_keep_memory(dev);
     const int pitch = pitch_of(H, W);
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    const size_t skwElem = fused ? 0 : elem;  // bytes per sample of skwDEM
     if (sweep_lds_bytes(std::max(H, W), f64) + 64 > (size_t)lds_limit(dev))  // + the kernels' static LDS
         return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)%s",
                     std::max(H, W), f64 ? "double" : "float", lds_limit(dev),
@@ -309,17 +312,21 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
             S.push_back(plan_sector(k, n, H, W, dx, R));
             if ((flags & TVS_FLAG_COMPACT) || fixed) compact_layout(S.back());
         }
+    // the gathering sweep reads the 45..135 deg frames from the transposed grid
+    bool needT = false;
+    for (const Sector &s : S) needT |= fused && (s.kase == 1 || s.kase == 2);
+    const size_t demTBytes = needT ? (size_t)H * W * sizeof(float) : 0;
     const int tabN = std::max(H, W);  // entries for m = 1 .. max(H, W)
     const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
     const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
     constexpr int kWorkSlots = 64;  // evaluation counters of the sweep (TVS_FLAG_COUNT_EVALS)
-    // every carved piece is rounded up to 256 bytes: at most 5 pieces besides the skewed buffers
-    const size_t fixedParts = tabBytes + kahanBytes + 256 * 4 + kWorkSlots * 8 + 6 * 256;
+    // every carved piece is rounded up to 256 bytes: at most 6 pieces besides the skewed buffers
+    const size_t fixedParts = tabBytes + kahanBytes + demTBytes + 256 * 4 + kWorkSlots * 8 + 7 * 256;
     if (fixed && fixed_bytes <= fixedParts)
         return fail(TVS_ERANGE, "tables of a %d x %d grid (%zu bytes) exceed the %zu-byte allocation-free scratch",
                     H, W, fixedParts, fixed_bytes);
     const size_t chunkBudget = fixed ? fixed_bytes - fixedParts : budget ? budget : scratch_budget();
-    const std::vector<Chunk> chunks = make_chunks(S, elem, pitch, chunkBudget);
+    const std::vector<Chunk> chunks = make_chunks(S, skwElem, pitch, chunkBudget);
     size_t maxChunk = 0;
     for (const Chunk &c : chunks) maxChunk = std::max(maxChunk, c.bytes);
     if (fixed && maxChunk > chunkBudget)
@@ -327,7 +334,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
                     "one sector of a %d x %d grid needs %zu bytes of skewed buffers; the allocation-free scratch "
                     "holds %zu",
                     H, W, maxChunk, chunkBudget);
-    const size_t total = tabBytes + kahanBytes + 256 * 4 + kWorkSlots * 8 + maxChunk;
+    const size_t total = fixedParts + maxChunk;
 
     Scratch scr;
     scr.st = st;
@@ -349,6 +356,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     float *ksum = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
     float *kc = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
     unsigned long long *work = count ? (unsigned long long *)carve(kWorkSlots * 8) : nullptr;
+    float *demT = needT ? (float *)carve(demTBytes) : nullptr;
     char *skwV = (char *)carve(maxChunk);
 
     Timer tm;
@@ -356,19 +364,27 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     tm.st = st;
     HIPCHK(launch_divtab(tab32, tab64, tabN, st));
     if (work) HIPCHK(launch_fill_u32((uint32_t *)work, 2 * kWorkSlots, 0u, st));
+    if (needT) {
+        HIPCHK(tm.begin(0));
+        HIPCHK(launch_transpose(d_dem, demT, H, W, st));
+        HIPCHK(tm.mark());
+    }
     int64_t evals = 0, pairs = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const Chunk &c = chunks[ci];
         ChunkArgs a = chunk_args(S, c, H, W, pitch, h0);
-        const int64_t elems = (int64_t)(c.bytes / (elem + sizeof(uint32_t)));
-        void *skw = skwV;
-        uint32_t *V = (uint32_t *)(skwV + (size_t)elems * elem);
+        const int64_t elems = (int64_t)(c.bytes / (skwElem + sizeof(uint32_t)));
+        void *skw = fused ? nullptr : skwV;
+        uint32_t *V = (uint32_t *)(skwV + (size_t)elems * skwElem);
         if (d_debugV) HIPCHK(launch_fill_u32(V, elems, 0xFFFFFFFFu, st));
-        HIPCHK(tm.begin(0));
-        HIPCHK(launch_relocate(a, c.maxWx, c.maxRows, d_dem, skw, f64, st));
-        HIPCHK(tm.mark());
+        if (!fused) {
+            HIPCHK(tm.begin(0));
+            HIPCHK(launch_relocate(a, c.maxWx, c.maxRows, d_dem, skw, f64, st));
+            HIPCHK(tm.mark());
+        }
         HIPCHK(tm.begin(1));
-        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, skw, V, tab32, tab64, f64, scan, rcp, prune, work, st));
+        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, d_dem, demT, skw, V, tab32, tab64, f64, scan, rcp, prune, work,
+                            st));
         HIPCHK(tm.mark());
         if (d_debugV) {
             const Sector &s = S[0];
@@ -396,8 +412,10 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         stats->chunks = (int32_t)chunks.size();
         stats->los_evals = evals;
         stats->pov_sector_pairs = pairs;
-        stats->reloc_bytes = pairs * (int64_t)(4 + elem);
-        stats->sweep_bytes = pairs * (int64_t)(elem + 4);
+        // relocation: 4 B read + the element written per sample; fused, only the transposition of the grid
+        stats->reloc_bytes = fused ? (int64_t)(2 * demTBytes) : pairs * (int64_t)(4 + elem);
+        // sweep: the row's elevations read (4 B of grid, or the skwDEM element) + 4 B of ring sums written
+        stats->sweep_bytes = pairs * (int64_t)((fused ? 4 : elem) + 4);
         stats->scratch_bytes = (int64_t)total;
         if (work) {
             unsigned long long h[kWorkSlots];
@@ -573,7 +591,8 @@ int total_on_stream(const float *d_dem, int H, int W, double dx, double h0, int 
 
 size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t flags, size_t budget) {
     const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
-    const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    const bool fused = (flags & TVS_FLAG_RELOCATE) == 0;
+    const size_t elem = fused ? 0 : f64 ? sizeof(double) : sizeof(float);
     std::vector<Sector> S;
     for (int k = 0; k < n; ++k) {
         S.push_back(plan_sector(k, n, H, W, dx, R));
@@ -584,7 +603,8 @@ size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t fl
         maxChunk = std::max(maxChunk, c.bytes);
     const size_t tab = (size_t)std::max(H, W) * (sizeof(float2) + sizeof(double2));
     const size_t kahan = (flags & TVS_FLAG_ACC_KAHAN32) ? (size_t)H * W * 2 * sizeof(float) : 0;
-    return tab + kahan + 256 * 4 + 64 * 8 + maxChunk + 6 * 256;
+    const size_t demT = (fused && n >= 2) ? (size_t)H * W * sizeof(float) : 0;
+    return tab + kahan + demT + 256 * 4 + 64 * 8 + maxChunk + 7 * 256;
 }
 
 }  // namespace host

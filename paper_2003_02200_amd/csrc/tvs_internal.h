@@ -86,9 +86,14 @@ struct SingQuery {
 hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st);
 hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, void *skw,
                            bool f64, hipStream_t st);
-hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
-                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
-                        unsigned long long *work, hipStream_t st);
+// The sweep of a chunk. With skw null every workgroup gathers its skewed row from the grid (demT, the
+// transposed grid, serves the 45..135 deg axes; null reads the grid down its columns); otherwise it
+// reads the row from the skwDEM buffer the relocation wrote.
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
+                        const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
+                        bool rcp, bool prune, unsigned long long *work, hipStream_t st);
+// demT[j][i] = dem[i][j] for an H x W grid.
+hipError_t launch_transpose(const float *dem, float *demT, int H, int W, hipStream_t st);
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum,
                            float *kahan_c, int first, int last, hipStream_t st);
 hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV, bool f64, bool rcp,

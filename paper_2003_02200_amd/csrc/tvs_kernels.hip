@@ -212,6 +212,40 @@ __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     for (int64_t x = i; x < n; x += stride) p[x] = v;
 }
 
+// A sector's base frame X (Hx x Wx) as strides into the DEM: X[p][q] = base[p * rs + q * cs]. With
+// the transposed grid `demT` (W x H, row-major) the frames of the 45..135 deg axes (cases 1 and 2)
+// read along rows of demT, so consecutive columns q of X are consecutive addresses in every case.
+struct FrameRef {
+    const float *base;
+    int64_t rs;
+    int64_t cs;
+};
+__device__ __forceinline__ FrameRef frame_ref(int kase, int H, int W, const float *dem, const float *demT) {
+    switch (kase) {
+    case 0: return FrameRef{dem, W, 1};
+    case 1: return demT ? FrameRef{demT, H, 1} : FrameRef{dem, 1, W};
+    case 2: return demT ? FrameRef{demT + (int64_t)(W - 1) * H, -(int64_t)H, 1} : FrameRef{dem + (W - 1), -1, W};
+    default: return FrameRef{dem + (W - 1), W, -1};
+    }
+}
+
+// demT[j][i] = dem[i][j] for an H x W grid: 64 x 64 tiles through LDS (pitch 65), both sides coalesced.
+__global__ __launch_bounds__(256) void k_transpose(const float *__restrict__ dem, float *__restrict__ demT, int H,
+                                                   int W) {
+    __shared__ float t[64 * 65];
+    const int i0 = blockIdx.y * 64, j0 = blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int r = wv; r < 64; r += 4) {
+        const int i = i0 + r, j = j0 + lane;
+        if (i < H && j < W) t[r * 65 + lane] = dem[(int64_t)i * W + j];
+    }
+    __syncthreads();
+    for (int r = wv; r < 64; r += 4) {
+        const int j = j0 + r, i = i0 + lane;
+        if (i < H && j < W) demT[(int64_t)j * H + i] = t[lane * 65 + r];
+    }
+}
+
 // --------------------------------------------------------------------------- relocation
 // A workgroup owns a strip of 64 base-frame columns of one sector and walks down RL_SEG of its
 // skewed rows in batches of 32. Skewed row t of column j blends base rows t + d_j and t + d_j + 1,
@@ -617,22 +651,70 @@ __device__ __forceinline__ int row_of_block(int b, int N) {
     return (b & 1) ? c + ((b + 1) >> 1) : c - (b >> 1);
 }
 
-// Load skewed row `ri` (existing samples jlo..jlo+nt-1) into LDS with TVS_SWEEP_PAD -inf
-// sentinels on both sides. Returns nt (0 for an empty row).
+// Skewed row ri of sector s gathered straight from the base frame into LDS (Alg. 6's interpolation:
+// the double blend (1 - r_j) X[u][j] + r_j X[u + 1][j], rows clamped, -0 made +0), with
+// TVS_SWEEP_PAD -inf sentinels on both sides, so that no skwDEM buffer exists in HBM. Consecutive
+// samples read consecutive columns of X: coalesced when the frame's columns are contiguous (the DEM
+// for the 0..45 and 135..180 deg axes, its transpose for the others); neighbouring skewed rows
+// reuse the same cache lines. Returns nt (0 for an empty row).
 template <typename Tz>
-__device__ __forceinline__ int load_row(const ChunkArgs &a, const SecDev &s, int ri, const Tz *skw, Tz *row,
-                                        int &jlo) {
-    int Hx, Wx;
-    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+__device__ __forceinline__ int gather_row(const FrameRef &F, int Hx, int Wx, const SecDev &s, int ri, Tz *row,
+                                          int &jlo) {
     const int t = s.t0 + ri;
     jlo = row_first(s.T, t, Hx, Wx);
     const int jhi = row_last(s.T, t, Hx, Wx);
     const int nt = jhi - jlo + 1;
     if (nt <= 0) return 0;
-    const Tz *src = skw + skw_row(s, t, a.pitch) + jlo;
     for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
         const int q = x - TVS_SWEEP_PAD;
-        row[x] = (q >= 0 && q < nt) ? src[q] : neg_inf<Tz>();
+        Tz v = neg_inf<Tz>();
+        if (q >= 0 && q < nt) {
+            const int j = jlo + q;
+            int d;
+            double r;
+            col_offset(s.T, j, d, r);
+            const int u = t + d;
+            const float *col = F.base + (int64_t)j * F.cs;
+            const float av = col[(int64_t)min(max(u, 0), Hx - 1) * F.rs];
+            double z = (double)av;
+            if (r != 0.0 && u >= 0 && u < Hx - 1) {
+                const float bv = col[(int64_t)(u + 1) * F.rs];
+                z = __dadd_rn(__dmul_rn(__dsub_rn(1.0, r), (double)av), __dmul_rn(r, (double)bv));
+            }
+            v = add_rn((Tz)z, (Tz)0);
+        }
+        row[x] = v;
+    }
+    __syncthreads();
+    return nt;
+}
+
+// Where a single-grid sweep takes its rows: gathered from the grid (and its transpose), or read
+// from the skwDEM buffer the relocation kernel wrote.
+struct RowSrc {
+    const float *dem;
+    const float *demT;  // null: cases 1 and 2 read the DEM down its columns
+    int gather;         // 1: gather from the grid; 0: read skwDEM
+    int pad;
+};
+
+// Skewed row `ri` (existing samples jlo..jlo+nt-1) into LDS with TVS_SWEEP_PAD -inf sentinels on both
+// sides, from the grid or from skwDEM. Returns nt (0 for an empty row).
+template <typename Tz>
+__device__ __forceinline__ int load_row(const ChunkArgs &a, const RowSrc &src, const SecDev &s, int ri,
+                                        const Tz *skw, Tz *row, int &jlo) {
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    if (src.gather) return gather_row<Tz>(frame_ref(s.kase, a.H, a.W, src.dem, src.demT), Hx, Wx, s, ri, row, jlo);
+    const int t = s.t0 + ri;
+    jlo = row_first(s.T, t, Hx, Wx);
+    const int jhi = row_last(s.T, t, Hx, Wx);
+    const int nt = jhi - jlo + 1;
+    if (nt <= 0) return 0;
+    const Tz *src_row = skw + skw_row(s, t, a.pitch) + jlo;
+    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
+        const int q = x - TVS_SWEEP_PAD;
+        row[x] = (q >= 0 && q < nt) ? src_row[q] : neg_inf<Tz>();
     }
     __syncthreads();
     return nt;
@@ -703,7 +785,7 @@ __device__ __forceinline__ void add_work(unsigned long long *work, unsigned long
 }
 
 template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE = 0>
-__global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *__restrict__ skw,
+__global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowSrc src, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
                                                    const typename Tab<Tz>::type *__restrict__ tab,
                                                    unsigned long long *__restrict__ work) {
@@ -714,7 +796,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
     if ((int)blockIdx.x >= s.nrows) return;
     const int ri = row_of_block(blockIdx.x, s.nrows);
     int jlo;
-    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
+    const int nt = load_row<Tz>(a, src, s, ri, skw, row, jlo);
     if (nt == 0) return;
     if (work && threadIdx.x == 0) wg_work = 0;
     const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE, SLIDE>(row, nt, s.K, h0_of<Tz>(a), tab,
@@ -724,43 +806,6 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const Tz *
 }
 
 // ------------------------------------------------------------------- batched, fused sweep
-// Skewed row ri of a sector gathered straight from the DEM into LDS, with the relocation's
-// interpolation (the same FP64 blend, rows clamped, -0 made +0), so the batched path needs no
-// skwDEM buffer in HBM. Reads along a skewed row touch one grid row (cases 0/3) or one grid
-// column (cases 1/2) per sample; neighbouring skewed rows reuse the same cache lines.
-template <typename Tz>
-__device__ __forceinline__ int gather_row(const float *__restrict__ dem, int H, int W, const SecDev &s, int ri,
-                                          Tz *row, int &jlo) {
-    int Hx, Wx;
-    frame_dims(s.kase, H, W, Hx, Wx);
-    const int t = s.t0 + ri;
-    jlo = row_first(s.T, t, Hx, Wx);
-    const int jhi = row_last(s.T, t, Hx, Wx);
-    const int nt = jhi - jlo + 1;
-    if (nt <= 0) return 0;
-    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
-        const int q = x - TVS_SWEEP_PAD;
-        Tz v = neg_inf<Tz>();
-        if (q >= 0 && q < nt) {
-            const int j = jlo + q;
-            int d;
-            double r;
-            col_offset(s.T, j, d, r);
-            const int u = t + d;
-            const float av = dem[frame_index(s.kase, W, min(max(u, 0), Hx - 1), j)];
-            double z = (double)av;
-            if (r != 0.0 && u >= 0 && u < Hx - 1) {
-                const float bv = dem[frame_index(s.kase, W, u + 1, j)];
-                z = __dadd_rn(__dmul_rn(__dsub_rn(1.0, r), (double)av), __dmul_rn(r, (double)bv));
-            }
-            v = add_rn((Tz)z, (Tz)0);
-        }
-        row[x] = v;
-    }
-    __syncthreads();
-    return nt;
-}
-
 template <typename Tz> __device__ __forceinline__ Tz h0_of(const BatchEnt &e);
 template <> __device__ __forceinline__ float h0_of<float>(const BatchEnt &e) { return e.h0f; }
 template <> __device__ __forceinline__ double h0_of<double>(const BatchEnt &e) { return e.h0; }
@@ -790,7 +835,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         const BatchEnt &E = ent[item >> 16];
         const int ri = (int)(item & 0xffffu);
         int jlo;
-        const int nt = gather_row<Tz>(E.dem, E.H, E.W, E.s, ri, row, jlo);
+        int Hx, Wx;
+        frame_dims(E.s.kase, E.H, E.W, Hx, Wx);
+        const int nt = gather_row<Tz>(frame_ref(E.s.kase, E.H, E.W, E.dem, nullptr), Hx, Wx, E.s, ri, row, jlo);
         if (nt > 0)
             evals += sweep_row<Tz, NW, RCP, true, SLIDE>(row, nt, E.s.K, h0_of<Tz>(E), tab,
                                                          V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
@@ -803,8 +850,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
 // Comparison variant: one wavefront per POV and direction, lanes = 64 consecutive targets,
 // the running horizon is the exclusive wavefront prefix-max carried across 64-target chunks.
 template <typename Tz, int NW, bool RCP>
-__global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const Tz *__restrict__ skw,
-                                                        uint32_t *__restrict__ V,
+__global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const RowSrc src,
+                                                        const Tz *__restrict__ skw, uint32_t *__restrict__ V,
                                                         const typename Tab<Tz>::type *__restrict__ tab,
                                                         unsigned long long *__restrict__ work) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -813,7 +860,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_scan(const ChunkArgs a, const
     if ((int)blockIdx.x >= s.nrows) return;
     const int ri = row_of_block(blockIdx.x, s.nrows);
     int jlo;
-    const int nt = load_row<Tz>(a, s, ri, skw, row, jlo);
+    const int nt = load_row<Tz>(a, src, s, ri, skw, row, jlo);
     if (nt == 0) return;
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -1296,6 +1343,11 @@ hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st) {
     return hipGetLastError();
 }
 
+hipError_t launch_transpose(const float *dem, float *demT, int H, int W, hipStream_t st) {
+    k_transpose<<<dim3((W + 63) / 64, (H + 63) / 64), 256, 0, st>>>(dem, demT, H, W);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st) {
     const int64_t blocks = (n + 255) / 256;
     k_fill_u32<<<(unsigned)(blocks < 65536 ? (blocks > 0 ? blocks : 1) : 65536), 256, 0, st>>>(p, n, v);
@@ -1328,18 +1380,19 @@ static hipError_t set_lds(F f, size_t bytes) {
 }
 
 template <typename Tz>
-static hipError_t sweep_go(void (*f)(ChunkArgs, const Tz *, uint32_t *, const typename Tab<Tz>::type *,
+static hipError_t sweep_go(void (*f)(ChunkArgs, RowSrc, const Tz *, uint32_t *, const typename Tab<Tz>::type *,
                                      unsigned long long *),
-                           int nw, dim3 grid, size_t lds, hipStream_t st, const ChunkArgs &a, const void *skw,
-                           uint32_t *V, const typename Tab<Tz>::type *tab, unsigned long long *work) {
+                           int nw, dim3 grid, size_t lds, hipStream_t st, const ChunkArgs &a, const RowSrc &src,
+                           const void *skw, uint32_t *V, const typename Tab<Tz>::type *tab,
+                           unsigned long long *work) {
     hipError_t e = set_lds(f, lds);
     if (e != hipSuccess) return e;
-    f<<<grid, 64 * nw, lds, st>>>(a, (const Tz *)skw, V, tab, work);
+    f<<<grid, 64 * nw, lds, st>>>(a, src, (const Tz *)skw, V, tab, work);
     return hipGetLastError();
 }
 
 template <int NW>
-static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void *skw, uint32_t *V,
+static hipError_t sweep_nw(const ChunkArgs &a, const RowSrc &src, dim3 grid, size_t lds, const void *skw, uint32_t *V,
                            const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
                            int slide, unsigned long long *work, hipStream_t st) {
     constexpr int S6 = RMQ_LEVELS, S7 = RMQ_LEVELS + 1;
@@ -1347,22 +1400,22 @@ static hipError_t sweep_nw(const ChunkArgs &a, dim3 grid, size_t lds, const void
         if (f64) {
             auto f = slide == S6 ? (rcp ? k_sweep<double, NW, true, true, S6> : k_sweep<double, NW, false, true, S6>)
                                  : (rcp ? k_sweep<double, NW, true, true, S7> : k_sweep<double, NW, false, true, S7>);
-            return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+            return sweep_go<double>(f, NW, grid, lds, st, a, src, skw, V, tab64, work);
         }
         auto f = slide == S6 ? (rcp ? k_sweep<float, NW, true, true, S6> : k_sweep<float, NW, false, true, S6>)
                              : (rcp ? k_sweep<float, NW, true, true, S7> : k_sweep<float, NW, false, true, S7>);
-        return sweep_go<float>(f, NW, grid, lds, st, a, skw, V, tab32, work);
+        return sweep_go<float>(f, NW, grid, lds, st, a, src, skw, V, tab32, work);
     }
     if (f64) {
         auto f = scan ? (rcp ? k_sweep_scan<double, NW, true> : k_sweep_scan<double, NW, false>)
                  : rcp ? (prune ? k_sweep<double, NW, true, true> : k_sweep<double, NW, true, false>)
                        : (prune ? k_sweep<double, NW, false, true> : k_sweep<double, NW, false, false>);
-        return sweep_go<double>(f, NW, grid, lds, st, a, skw, V, tab64, work);
+        return sweep_go<double>(f, NW, grid, lds, st, a, src, skw, V, tab64, work);
     }
     auto f = scan ? (rcp ? k_sweep_scan<float, NW, true> : k_sweep_scan<float, NW, false>)
                   : rcp ? (prune ? k_sweep<float, NW, true, true> : k_sweep<float, NW, true, false>)
                         : (prune ? k_sweep<float, NW, false, true> : k_sweep<float, NW, false, false>);
-    return sweep_go<float>(f, NW, grid, lds, st, a, skw, V, tab32, work);
+    return sweep_go<float>(f, NW, grid, lds, st, a, src, skw, V, tab32, work);
 }
 
 // Waves per sweep workgroup: a workgroup holds one row in LDS, so long rows leave room for few
@@ -1376,9 +1429,10 @@ int sweep_waves(size_t lds) {
     return 16;
 }
 
-hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *skw, uint32_t *V,
-                        const float2 *tab32, const double2 *tab64, bool f64, bool scan, bool rcp, bool prune,
-                        unsigned long long *work, hipStream_t st) {
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
+                        const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
+                        bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
+    RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
     const dim3 grid(maxRows, a.nsec);
     ChunkArgs b = a;
     int maxK = 0, slide = 0;
@@ -1386,9 +1440,9 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const void *
     // without the early exit or in the lane-per-target variant no sliding maxima
     const size_t lds = sweep_lds_launch(maxWx, f64, prune && !scan ? maxK : INT_MAX, b.rmq, slide);
     switch (sweep_waves(lds)) {
-    case 4: return sweep_nw<4>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
-    case 8: return sweep_nw<8>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
-    default: return sweep_nw<16>(b, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
+    case 4: return sweep_nw<4>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
+    case 8: return sweep_nw<8>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
+    default: return sweep_nw<16>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
     }
 }
 

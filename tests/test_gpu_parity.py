@@ -153,6 +153,19 @@ def test_sector_rays_bitexact_double(tvs, orc, H, W, n, R, kind):
         assert np.array_equal(tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=EXACT), g)
 
 
+@pytest.mark.parametrize("H,W,n,R,kind", SHAPES[1::2])
+def test_sector_rays_relocation_kernel(tvs, orc, H, W, n, R, kind):
+    """TVS_FLAG_RELOCATE: the relocation kernel writes skwDEM and the sweep reads it; the same ring
+    sums as the oracle (and as the default sweep, which gathers its rows from the grid)."""
+    dem = _dem(H, W, kind, seed=9)
+    for k in _sectors(n):
+        for flags, prec in MODES[::2]:
+            note(f"sector_rays relocate H={H} W={W} n={n} R={R} k={k} flags={flags}")
+            g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=tvs.FLAG_RELOCATE | flags)
+            o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=prec)
+            assert np.array_equal(g, packed(o)), f"k={k} flags={flags}"
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", SHAPES[1::3])
 def test_sector_rays_prefix_max_variant(tvs, orc, H, W, n, R, kind):
     """The lane-per-target sweep (wavefront prefix-max horizon) gives the same integers."""
@@ -292,6 +305,9 @@ def test_total_compact_layout(tvs, orc, H, W, n, R, kind):
         comp, st_c = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=flags | tvs.FLAG_COMPACT, stats=True)
         assert np.array_equal(plain, comp), f"flags={flags}"
         assert st_c.scratch_bytes <= st_p.scratch_bytes and st_c.chunks <= st_p.chunks
+        # the relocation kernel and skwDEM (plain and compacted) give the gathering sweep's map
+        for extra in (tvs.FLAG_RELOCATE, tvs.FLAG_RELOCATE | tvs.FLAG_COMPACT):
+            assert np.array_equal(tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=flags | extra), plain), extra
         np.testing.assert_allclose(comp, orc.total(dem, 10.0, 1.5, n, R, prec=prec), rtol=1e-12, atol=0)
         plain0 = plain if plain0 is None else plain0
     scan = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_SWEEP_SCAN | tvs.FLAG_COMPACT)
