@@ -185,11 +185,12 @@ int tvs_multiple_viewshed(const float *d_dem, int32_t rows, int32_t cols, double
  * device buffer of the call (reciprocal tables, skewed elevation and viewshed buffers) is carved
  * from a static device array of TVS_NOALLOC_SCRATCH_BYTES that the library holds on each device it
  * runs on until the process ends (its address is looked up on a device's first call). The skewed
- * buffers take the compacted layout (TVS_FLAG_COMPACT) and the sectors are processed in groups
+ * viewshed rows take the compacted layout (TVS_FLAG_COMPACT) and the sectors are processed in groups
  * that fit the array; the map is the same as tvs_total_viewshed_async's, bit for bit.
- * Limit: one sector's skewed buffers, about 12 * (H_x + 1) * P bytes (H_x the sector's rows in its
- * 0..45 deg frame, P = max(rows, cols) rounded up to 64), must fit the array with the tables;
- * larger grids return TVS_ERANGE before any work is enqueued (sides up to about 4,700).
+ * Limit: one sector's skewed viewshed rows, 4 * (H_x + 1) * P bytes (H_x the sector's rows in its
+ * 0..45 deg frame, P = max(rows, cols) rounded up to 64), must fit the array together with the
+ * transposed grid (4 * rows * cols bytes) and the reciprocal tables (24 * max(rows, cols) bytes);
+ * larger grids return TVS_ERANGE before any work is enqueued (square grids up to about 5,700).
  * Calls on one device share the array: calls whose work overlaps on a device (other streams,
  * other host threads) race and must be serialised by the caller. The call itself allocates no
  * device memory, frees none and calls no allocating library routine. */
