@@ -23,9 +23,10 @@
  *            index distance m < rho = max_dist cos(s') / spacing and its last ring is
  *            clipped at rho.
  * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE. A skewed row is held in the
- *            LDS of one workgroup: with the default double elevations that caps the longer side
- *            at about 19,000 (TVS_ERANGE beyond; TVS_FLAG_SLOPE_F32 rows take half the bytes
- *            per sample and reach 32767).
+ *            LDS of one workgroup when it fits (float rows always; double rows up to about 19,800
+ *            samples); longer rows are swept in pieces whose targets stream through LDS windows,
+ *            every line of sight walked to its end (no early exit). The lane-per-target sweep
+ *            (TVS_FLAG_SWEEP_SCAN) and batches hold whole rows and return TVS_ERANGE beyond.
  * Results    Areas in square metres, double.
  *
  * Errors: every call returns TVS_OK (0) or a negative status; on error the outputs are
@@ -48,14 +49,14 @@
 extern "C" {
 #endif
 
-#define TVS_ABI_VERSION 7
+#define TVS_ABI_VERSION 8
 
 enum tvs_status {
     TVS_OK = 0,
     TVS_EINVAL = -1,  /* bad argument: null pointer, size, non-finite value, POV outside the grid */
     TVS_ENOMEM = -2,  /* host or device allocation failed */
     TVS_EDEVICE = -3, /* a HIP call or kernel launch failed (see tvs_last_error) */
-    TVS_ERANGE = -4,  /* grid side above 32767 (or a row longer than the workgroup LDS holds) */
+    TVS_ERANGE = -4,  /* grid side above 32767, or a row the LDS cannot hold where whole rows are needed */
     TVS_ETIMEDOUT = -5 /* tvs_server_wait: the request did not finish within the timeout */
 };
 

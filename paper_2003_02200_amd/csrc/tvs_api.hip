@@ -300,10 +300,9 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const int pitch = pitch_of(H, W);
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
     const size_t skwElem = fused ? 0 : elem;  // bytes per sample of skwDEM
-    if (sweep_lds_bytes(std::max(H, W), f64) + 64 > (size_t)lds_limit(dev))  // + the kernels' static LDS
-        return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS (%d bytes)%s",
-                    std::max(H, W), f64 ? "double" : "float", lds_limit(dev),
-                    f64 ? "; TVS_FLAG_SLOPE_F32 takes float rows" : "");
+    if (scan && !sweep_row_fits(std::max(H, W), f64))
+        return fail(TVS_ERANGE, "the lane-per-target sweep holds whole rows: %d %s samples do not fit the workgroup "
+                    "LDS (%d bytes)", std::max(H, W), f64 ? "double" : "float", lds_limit(dev));
 
     std::vector<Sector> S;
     if (debug_sector >= 0) S.push_back(plan_sector(debug_sector, n, H, W, dx, R));  // plain rows, copied out

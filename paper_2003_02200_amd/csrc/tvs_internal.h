@@ -92,6 +92,10 @@ hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const flo
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
                         bool rcp, bool prune, unsigned long long *work, hipStream_t st);
+// Does a skewed row of maxWx samples (with its sentinels) fit one workgroup's LDS? Longer rows are
+// swept in pieces that stream their targets through LDS windows (any flags but the lane-per-target
+// sweep, which needs whole rows).
+bool sweep_row_fits(int maxWx, bool f64);
 // demT[j][i] = dem[i][j] for an H x W grid.
 hipError_t launch_transpose(const float *dem, float *demT, int H, int W, hipStream_t st);
 hipError_t launch_backproj(const ChunkArgs &a, const uint32_t *V, double *out, float *kahan_sum,

@@ -805,6 +805,117 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowS
     if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
+// ---------------------------------------------------------- rows longer than the LDS holds
+// A skewed row too long for one workgroup's LDS (double rows beyond about 19,800 samples) is swept
+// in pieces: workgroup (row, piece) owns the piece's 64 NW consecutive POVs, one 64-POV segment per
+// wavefront, and streams the targets of both directions through an LDS window. Window c holds the
+// samples of steps 1 + cM .. (c + 1) M of every POV of the piece (M + 64 NW - 1 samples, a multiple-of-32
+// M, -inf outside the row); every lane carries its horizon, bit mask and ring sums from one window to
+// the next, so each line of sight is walked in order over the whole row, as in the single-window sweep
+// (a 32-step block never straddles two windows; the clipped step K may open the next one). Every target
+// in range is evaluated (no early exit). Samples come from the grid (gathered with the relocation's
+// interpolation) or from skwDEM.
+template <typename Tz, int NW, bool RCP>
+__global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const RowSrc src,
+                                                        const Tz *__restrict__ skw, uint32_t *__restrict__ V,
+                                                        const typename Tab<Tz>::type *__restrict__ tab, int M,
+                                                        int pieces, unsigned long long *__restrict__ work) {
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    Tz *win = reinterpret_cast<Tz *>(lds_raw);
+    __shared__ unsigned long long wg_work;
+    const SecDev &s = a.s[blockIdx.y];
+    const int ri = (int)blockIdx.x / pieces, piece = (int)blockIdx.x % pieces;
+    if (ri >= s.nrows) return;
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    const int t = s.t0 + ri;
+    const int jlo = row_first(s.T, t, Hx, Wx);
+    const int nt = row_last(s.T, t, Hx, Wx) - jlo + 1;
+    const int P0 = piece * 64 * NW;
+    if (nt <= 0 || P0 >= nt) return;  // uniform over the workgroup
+    const FrameRef F = frame_ref(s.kase, a.H, a.W, src.dem, src.demT);
+    const Tz *srow = src.gather ? nullptr : skw + skw_row(s, t, a.pitch) + jlo;
+    // elevation of sample p (0 <= p < nt) of the row
+    auto sample = [&](int p) -> Tz {
+        if (!src.gather) return srow[p];
+        const int j = jlo + p;
+        int d;
+        double r;
+        col_offset(s.T, j, d, r);
+        const int u = t + d;
+        const float *col = F.base + (int64_t)j * F.cs;
+        const float av = col[(int64_t)min(max(u, 0), Hx - 1) * F.rs];
+        double z = (double)av;
+        if (r != 0.0 && u >= 0 && u < Hx - 1) {
+            const float bv = col[(int64_t)(u + 1) * F.rs];
+            z = __dadd_rn(__dmul_rn(__dsub_rn(1.0, r), (double)av), __dmul_rn(r, (double)bv));
+        }
+        return add_rn((Tz)z, (Tz)0);
+    };
+    const int L = M + 64 * NW - 1;
+    const int lane = threadIdx.x & 63;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int q0 = P0 + 64 * wv, q = q0 + lane;
+    const bool live = q < nt;
+    const int K = s.K;
+    const Tz h = live ? add_rn(sample(q), h0_of<Tz>(a)) : neg_inf<Tz>();
+    uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
+    uint32_t e = (K >= 1) ? 0u : 2u;
+    unsigned long long evals = 0;
+    const int last = min(nt - 1, P0 + 64 * NW - 1);  // the piece's last POV
+#pragma unroll 1
+    for (int DIR = 1; DIR >= -1; DIR -= 2) {
+        // steps of this wavefront (its farthest-reaching lane) and of the whole piece (window count)
+        const int top = min(nt - 1, q0 + 63);
+        const int mb = q0 >= nt ? 0 : DIR > 0 ? min(K, nt - 1 - q0) : min(K, top);
+        const int mbW = DIR > 0 ? min(K, nt - 1 - P0) : min(K, last);
+        const int mfull = (mb == K) ? K - 1 : mb;
+        const int nwin = mbW >= 1 ? (mbW + M - 1) / M : 0;
+        Tz mx = neg_inf<Tz>();
+        RingAcc ra;
+        uint32_t bits = 0, acc = 0;
+        int m = 1;
+        for (int c = 0; c < nwin; ++c) {
+            __syncthreads();  // the previous window is no longer read
+            const int origin = DIR > 0 ? P0 + 1 + c * M : P0 - (c + 1) * M;
+            for (int x = threadIdx.x; x < L; x += blockDim.x) {
+                const int p = origin + x;
+                win[x] = (p >= 0 && p < nt) ? sample(p) : neg_inf<Tz>();
+            }
+            __syncthreads();
+            const int wend = (c + 1) * M;  // last step held by this window
+            // position q + DIR m sits at zb[DIR m]
+            const Tz *zb = win + (q - P0) + (DIR > 0 ? -1 - c * M : (c + 1) * M);
+            for (; m + 31 <= min(mfull, wend); m += 32) {
+                const auto *tt = tab + (m - 1);
+#pragma unroll
+                for (int k = 0; k < 32; ++k) vis_step(slope<RCP>(sub_rn(zb[DIR * (m + k)], h), tt[k]), mx, bits);
+                if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
+            }
+            if (m <= mfull && mfull <= wend) {  // the last steps of the wavefront, all in this window
+                for (; m <= mfull; ++m) {
+                    const Tz th = slope<RCP>(sub_rn(zb[DIR * m], h), tab[m - 1]);
+                    acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
+                    mx = vmax_plain(mx, th);
+                }
+            }
+            // the clipped last ring, when this window holds step K
+            if (mb == K && K >= 1 && m == K && K <= wend) {
+                e += slope<RCP>(sub_rn(zb[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
+                m = K + 1;
+            }
+        }
+        U += ra.total() + acc;
+        if (live) evals += (unsigned long long)(DIR > 0 ? min(K, nt - 1 - q) : min(K, q));
+    }
+    if (live) V[skw_row(s, t, a.pitch) + jlo + q] = U | (e << 30);
+    if (work) {
+        if (threadIdx.x == 0) wg_work = 0;
+        __syncthreads();
+        add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
+    }
+}
+
 // ------------------------------------------------------------------- batched, fused sweep
 template <typename Tz> __device__ __forceinline__ Tz h0_of(const BatchEnt &e);
 template <> __device__ __forceinline__ float h0_of<float>(const BatchEnt &e) { return e.h0f; }
@@ -1306,23 +1417,28 @@ constexpr int SLIDE_MAX_K = 1900, SLIDE_MAX_K_LONG = 3900;
 // most maxK) allow it: RMQ_LEVELS, or RMQ_LEVELS + 1 for longer lines of sight, when the row with
 // those tables still fits as many workgroups per CU (up to the 8 four-wave workgroups a CU holds);
 // else 0. For double rows the 6-level tables take the bytes of the suffix and prefix maxima.
-static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &slide) {
-    const size_t nbx = (maxWx + 31) / 32;
-    const size_t base = sweep_lds_bytes(maxWx, f64);
-    const size_t full = base + (size_t)RMQ_LEVELS * nbx * sizeof(float);
-    // the device's limit, queried once per device (the first launch on it is not captured)
+// The current device's largest workgroup LDS, queried once per device (the first launch on it is not
+// captured): the same limit the host checks use, the opt-in maximum, else the default one.
+static int lds_cap() {
     static std::atomic<int> caps[64];
     int dev = 0, cap = 0;
     if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
         cap = caps[dev].load();
         if (cap == 0) {
-            // the same limit the host checks use: the opt-in maximum, else the default one
             if (hipDeviceGetAttribute(&cap, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess || cap <= 0)
                 if (hipDeviceGetAttribute(&cap, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
                     cap = 0;
             if (cap > 0) caps[dev].store(cap);
         }
     }
+    return cap;
+}
+
+static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &slide) {
+    const size_t nbx = (maxWx + 31) / 32;
+    const size_t base = sweep_lds_bytes(maxWx, f64);
+    const size_t full = base + (size_t)RMQ_LEVELS * nbx * sizeof(float);
+    const int cap = lds_cap();
     rmq = full + 64 <= (size_t)cap ? 1 : 0;  // + the kernels' static LDS
     slide = 0;
     if (rmq && maxK <= SLIDE_MAX_K_LONG) {
@@ -1429,10 +1545,48 @@ int sweep_waves(size_t lds) {
     return 16;
 }
 
+bool sweep_row_fits(int maxWx, bool f64) { return sweep_lds_bytes(maxWx, f64) + 64 <= (size_t)lds_cap(); }
+
+// Rows that do not fit the LDS: pieces of 512 POVs (8 waves), windows of M steps in about 80 KB of
+// LDS (M a multiple of 32, no larger than the longest line of sight of the chunk needs).
+static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int maxWx, int maxRows, int maxK,
+                                    const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64,
+                                    bool f64, bool rcp, unsigned long long *work, hipStream_t st) {
+    constexpr int NW = 8;
+    const size_t elem = f64 ? sizeof(double) : sizeof(float);
+    const int steps = std::max(1, std::min(maxK, maxWx));
+    const int mcap = (int)(((size_t)(80 * 1024) / elem - (64 * NW - 1)) / 32) * 32;
+    const int M = std::min(mcap, (steps + 31) / 32 * 32);
+    const size_t lds = (size_t)(M + 64 * NW - 1) * elem;
+    const int pieces = (maxWx + 64 * NW - 1) / (64 * NW);
+    const dim3 grid((unsigned)maxRows * (unsigned)pieces, a.nsec);
+#define TVS_LONG_GO(TZ, RC, TAB)                                                                         \
+    do {                                                                                                 \
+        auto f = k_sweep_long<TZ, NW, RC>;                                                               \
+        hipError_t e = set_lds(f, lds);                                                                  \
+        if (e != hipSuccess) return e;                                                                   \
+        f<<<grid, 64 * NW, lds, st>>>(a, src, (const TZ *)skw, V, TAB, M, pieces, work);                \
+    } while (0)
+    if (f64) {
+        if (rcp) TVS_LONG_GO(double, true, tab64);
+        else TVS_LONG_GO(double, false, tab64);
+    } else {
+        if (rcp) TVS_LONG_GO(float, true, tab32);
+        else TVS_LONG_GO(float, false, tab32);
+    }
+#undef TVS_LONG_GO
+    return hipGetLastError();
+}
+
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
                         bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
     RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
+    if (!sweep_row_fits(maxWx, f64)) {
+        int maxK = 0;
+        for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
+        return launch_sweep_long(a, src, maxWx, maxRows, maxK, skw, V, tab32, tab64, f64, rcp, work, st);
+    }
     const dim3 grid(maxRows, a.nsec);
     ChunkArgs b = a;
     int maxK = 0, slide = 0;

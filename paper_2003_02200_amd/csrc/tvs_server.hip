@@ -324,9 +324,9 @@ int check_request(tvs_server *s, int dem, double h0, int n, double R, uint32_t f
     if (flags & ~ok) return fail(TVS_EINVAL, "unsupported flags 0x%x for this request", flags);
     if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
         return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
-    if (total && sweep_lds_bytes(std::max(g.rows, g.cols), (flags & TVS_FLAG_SLOPE_F32) == 0) + 64 >
-                     (size_t)lds_limit(s->dev))
-        return fail(TVS_ERANGE, "grid %d x %d is too large for the default precision", g.rows, g.cols);
+    if (total && (flags & TVS_FLAG_SWEEP_SCAN) &&
+        sweep_lds_bytes(std::max(g.rows, g.cols), (flags & TVS_FLAG_SLOPE_F32) == 0) + 64 > (size_t)lds_limit(s->dev))
+        return fail(TVS_ERANGE, "grid %d x %d: the lane-per-target sweep holds whole rows in LDS", g.rows, g.cols);
     return TVS_OK;
 }
 

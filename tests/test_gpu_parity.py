@@ -254,13 +254,36 @@ def test_long_rows_bound_paths(tvs, orc, H, W, R, flags, prec):
     assert 0 < st.sweep_evals_done <= st.los_evals
 
 
-def test_double_rows_beyond_lds_rejected(tvs):
-    """Double rows of 25000 samples (within the side limit) do not fit a workgroup's LDS:
-    TVS_ERANGE, with the float path named in the message."""
-    dem = np.zeros((2, 25000), np.float32)
-    with pytest.raises(tvs.TvsError) as ei:
-        tvs.total_viewshed(dem, 10.0, 1.5, 2, 1000.0)
-    assert ei.value.status == -4 and "TVS_FLAG_SLOPE_F32" in str(ei.value)
+LONG_DOUBLE = [
+    # (H, W, n, R, sector whose skewed rows are the long ones): double rows of 25000 and 32767 samples,
+    # beyond what one workgroup's LDS holds; unbounded and bounded lines of sight
+    (2, 25000, 4, INF, 0),
+    (2, 25000, 4, 50000.0, 0),
+    (25000, 2, 4, INF, 2),  # the long rows in the transposed frame (the 90 deg axis)
+    (3, 32767, 4, INF, 0),
+    (3, 32767, 4, 30000.0, 0),
+]
+
+
+@pytest.mark.parametrize("H,W,n,R,k", LONG_DOUBLE)
+def test_double_rows_beyond_lds_streamed(tvs, orc, H, W, n, R, k):
+    """Rows longer than the LDS are swept in pieces that stream their targets through LDS windows,
+    each lane's horizon and ring sums carried from window to window: the ring sums of the long sector
+    bit for bit against the oracle (default and quotient decisions, rows gathered from the grid or
+    read from skwDEM), and the whole map against the oracle."""
+    long_side = max(H, W)
+    prof = (1000.0 + np.random.default_rng(43).normal(0.0, 4.0, (min(H, W), long_side)).cumsum(axis=1))
+    dem = np.ascontiguousarray((prof if W >= H else prof.T).astype(np.float32))
+    for flags, prec in ((0, P_DEFAULT), (F64, P_DOUBLE), (0x200, P_DEFAULT)):
+        note(f"long double rows H={H} W={W} n={n} R={R} k={k} flags={flags}")
+        g = tvs.debug_sector_rays(dem, 10.0, 1.5, n, R, k, flags=flags)
+        o = orc.sector_V(dem, 10.0, 1.5, n, R, k, prec=prec)
+        bad = np.argwhere(g != packed(o))
+        assert bad.size == 0, f"flags={flags}: {len(bad)} samples differ, first {bad[:3].tolist()}"
+    note(f"long double rows H={H} W={W} n={n} R={R}: total")
+    g, st = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_COUNT_EVALS, stats=True)
+    np.testing.assert_allclose(g, orc.total(dem, 10.0, 1.5, n, R, prec=P_DEFAULT), rtol=1e-12, atol=0)
+    assert st.sweep_evals_done == st.los_evals  # the streamed pieces walk every target in range
 
 
 @pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES[:3])
