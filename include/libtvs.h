@@ -255,19 +255,26 @@ int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_se
 
 /* ---- Request server: resident grids, continuous batching ------------------------------------
  * Clients on any thread submit total and singular viewshed requests against grids uploaded once.
- * A scheduler thread admits total requests in arrival order while their device memory (map plus
- * scratch, scratch capped at a quarter of the budget) fits hbm_budget_bytes, each on the next of
- * `streams` streams, so that requests arriving while others run start at once and overlap on the
- * device; waiting singular requests are launched together, up to max_singular_batch per launch
- * (one wavefront per line of sight of every query, then one area sum per query). A result does
- * not depend on what else runs (no atomics, fixed accumulation order). The server is this
- * library's, not the paper's; the computations are the paper's (Section 4.1, Alg. 1). */
+ * A scheduler thread admits total requests in arrival order while their device memory (maps plus
+ * scratch, scratch capped at a quarter of the budget) fits hbm_budget_bytes. Whenever one of two
+ * group slots is free, the waiting total requests of the front request's sector count and flags
+ * (up to max_total_batch) leave together as one batch (tvs_batch_create's launches: one persistent
+ * fused relocate + sweep launch over every request's skewed rows and one back-projection launch per
+ * sector chunk); totals that arrive while both groups run gather into the next group. Totals the
+ * batched sweep does not take (TVS_FLAG_ACC_KAHAN32, TVS_FLAG_SWEEP_SCAN, TVS_FLAG_NO_PRUNE, rows
+ * longer than the LDS holds) run alone on the next of `streams` streams, overlapping with the rest.
+ * Waiting singular requests are launched together, up to max_singular_batch per launch (one
+ * wavefront per line of sight of every query, then one area sum per query). A result does not
+ * depend on what else runs (no atomics, fixed accumulation order). The server is this library's,
+ * not the paper's; the computations are the paper's (Section 4.1, Alg. 1). */
 typedef struct tvs_server tvs_server; /* opaque */
 
 typedef struct tvs_server_config {
     int64_t hbm_budget_bytes;   /* 0: half the device memory free at creation */
     int32_t streams;            /* streams for total requests, 0: 4 (at most 16) */
     int32_t max_singular_batch; /* queries per singular launch, 0: 64 */
+    int32_t max_total_batch;    /* total requests per batched launch group, 0: 16 */
+    int32_t pad;
 } tvs_server_config;
 
 typedef struct tvs_request_result {
@@ -286,6 +293,8 @@ typedef struct tvs_server_stats {
     int64_t singular_batched;      /* singular requests they carried */
     int64_t max_concurrent_totals; /* most total requests on the device at once */
     int64_t budget_bytes, bytes_in_use, peak_bytes;
+    int64_t total_batches;         /* batched launch groups of total requests so far */
+    int64_t total_batched;         /* total requests they carried */
 } tvs_server_stats;
 
 /* Starts a server on the current HIP device (cfg may be NULL for the defaults). */

@@ -72,7 +72,8 @@ class BatchInfo(C.Structure):
 
 
 class ServerConfig(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_int64), ("streams", C.c_int32), ("max_singular_batch", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("streams", C.c_int32), ("max_singular_batch", C.c_int32),
+                ("max_total_batch", C.c_int32), ("pad", C.c_int32)]
 
 
 class RequestResult(C.Structure):
@@ -84,7 +85,7 @@ class ServerStats(C.Structure):
     _fields_ = [("grids", C.c_int32), ("pending", C.c_int32), ("running", C.c_int32), ("pad", C.c_int32),
                 ("completed", C.c_int64), ("singular_batches", C.c_int64), ("singular_batched", C.c_int64),
                 ("max_concurrent_totals", C.c_int64), ("budget_bytes", C.c_int64), ("bytes_in_use", C.c_int64),
-                ("peak_bytes", C.c_int64)]
+                ("peak_bytes", C.c_int64), ("total_batches", C.c_int64), ("total_batched", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
@@ -402,8 +403,9 @@ class Server:
     """A request server (tvs_server_*): resident grids, total and singular requests from any
     thread, continuous batching on the device. Results come back by ticket."""
 
-    def __init__(self, hbm_budget_bytes: int = 0, streams: int = 0, max_singular_batch: int = 0):
-        cfg = ServerConfig(hbm_budget_bytes, streams, max_singular_batch)
+    def __init__(self, hbm_budget_bytes: int = 0, streams: int = 0, max_singular_batch: int = 0,
+                 max_total_batch: int = 0):
+        cfg = ServerConfig(hbm_budget_bytes, streams, max_singular_batch, max_total_batch, 0)
         h = C.c_void_p()
         _check(lib().tvs_server_create(C.byref(cfg), C.byref(h)))
         self._h = h

@@ -404,6 +404,122 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
 
 }  // namespace
 
+namespace tvs {
+namespace host {
+
+bool batch_rows_fit(int maxWx, bool f64) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    return sweep_lds_bytes(maxWx, f64) + 64 <= (size_t)lds_limit(dev);
+}
+
+// A batch enqueued once on a stream, without a graph (the request server's groups of total requests):
+// the same plan, work lists and launches as a captured batch pass. The work lists go through the
+// caller's pinned staging buffer (grown here; the caller keeps it untouched until the stream has
+// passed this work), the device memory is taken and returned stream-ordered on `st`.
+int batch_enqueue(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, hipStream_t st, size_t budget,
+                  PinnedStaging &stage, int *out_chunks) {
+    tvs_batch b;
+    b.ntiles = ntiles;
+    b.n = n;
+    b.flags = flags;
+    b.f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
+    b.rcp = (flags & (TVS_FLAG_SLOPE_EXACT | TVS_FLAG_SLOPE_F64)) == 0;
+    b.tiles.assign(tiles, tiles + ntiles);
+    HIPCHK(hipGetDevice(&b.dev));
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        std::vector<Sector> S;
+        S.reserve(n);
+        for (int k = 0; k < n; ++k) S.push_back(plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist));
+        for (const Sector &x : S) b.maxK = std::max(b.maxK, std::min(x.K, std::max(x.Hx, x.Wx)));
+        b.sectors.push_back(std::move(S));
+        b.maxWx = std::max(b.maxWx, std::max(T.rows, T.cols));
+    }
+    b.tabN = b.maxWx;
+    if (!batch_rows_fit(b.maxWx, b.f64))
+        return fail(TVS_ERANGE, "a skewed row of %d samples does not fit the workgroup LDS", b.maxWx);
+    if (int rc = plan_chunks(&b, budget)) return rc;
+    std::vector<BatchEnt> ent;
+    std::vector<BatchTile> bt;
+    std::vector<uint32_t> items;
+    build_tables(&b, ent, bt, items);
+    size_t maxV = 0;
+    for (const ChunkPlan &c : b.chunks) maxV = std::max(maxV, c.vbytes);
+    const size_t nch = b.chunks.size();
+    const size_t sz_ent = align256(ent.size() * sizeof(BatchEnt)), sz_bt = align256(bt.size() * sizeof(BatchTile)),
+                 sz_items = align256(items.size() * sizeof(uint32_t));
+    const size_t sz_tab32 = align256((size_t)b.tabN * sizeof(float2)), sz_tab64 = align256((size_t)b.tabN * sizeof(double2)),
+                 sz_ctr = align256(nch * sizeof(unsigned int));
+    const size_t host_bytes = sz_ent + sz_bt + sz_items;
+    if (stage.cap < host_bytes) {
+        const size_t want = std::max(host_bytes, (size_t)2 * stage.cap);
+        if (stage.p) (void)hipHostFree(stage.p);
+        stage.p = nullptr;
+        stage.cap = 0;
+        HIPCHK(hipHostMalloc(&stage.p, want, hipHostMallocDefault));
+        stage.cap = want;
+    }
+    char *h = (char *)stage.p;
+    memcpy(h, ent.data(), ent.size() * sizeof(BatchEnt));
+    memcpy(h + sz_ent, bt.data(), bt.size() * sizeof(BatchTile));
+    memcpy(h + sz_ent + sz_bt, items.data(), items.size() * sizeof(uint32_t));
+    const size_t dev_bytes = host_bytes + sz_tab32 + sz_tab64 + sz_ctr + align256(maxV);
+    char *d = nullptr;
+    if (hipMallocAsync((void **)&d, dev_bytes, st) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(TVS_ENOMEM, "batch device memory of %zu bytes not available", dev_bytes);
+    }
+    b.ent = (BatchEnt *)d;
+    b.btiles = (BatchTile *)(d + sz_ent);
+    b.items = (uint32_t *)(d + sz_ent + sz_bt);
+    b.tab32 = (float2 *)(d + host_bytes);
+    b.tab64 = (double2 *)(d + host_bytes + sz_tab32);
+    b.counters = (unsigned int *)(d + host_bytes + sz_tab32 + sz_tab64);
+    b.V = (uint32_t *)(d + host_bytes + sz_tab32 + sz_tab64 + sz_ctr);
+    b.work = nullptr;
+    const int cus = cu_count(b.dev);
+    {
+        const auto key = std::make_tuple((int)b.f64, (int)b.rcp, ceil_log2(b.maxWx), ceil_log2(b.maxK + 1));
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) b.shape = it->second;
+    }
+    b.grid = cus * b.shape.per_cu;
+    hipError_t e = hipMemcpyAsync(d, h, host_bytes, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+        e = launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b.f64, b.rcp, b.shape.waves, 0,
+                               b.maxWx, b.maxK, nullptr, st);
+    if (e == hipSuccess) e = enqueue_pass(&b, st);
+    const hipError_t fe = hipFreeAsync(d, st);
+    if (e != hipSuccess) return fail(TVS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
+    if (fe != hipSuccess) return fail(TVS_EDEVICE, "batch scratch release: %s", hipGetErrorString(fe));
+    if (out_chunks) *out_chunks = (int)nch;
+    return TVS_OK;
+}
+
+// Device memory batch_enqueue takes for these tiles (beyond their maps), an upper bound.
+size_t batch_scratch_bytes(const tvs_tile *tiles, int ntiles, int n, size_t budget) {
+    int maxWx = 0;
+    size_t v = 0, nrows = 0;
+    for (int t = 0; t < ntiles; ++t) {
+        const tvs_tile &T = tiles[t];
+        maxWx = std::max(maxWx, std::max(T.rows, T.cols));
+        const int pitch = pitch_of(T.rows, T.cols);
+        for (int k = 0; k < n; ++k) {
+            const Sector s = plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist);
+            v += (size_t)s.prows * pitch * 4;
+            nrows += (size_t)s.nrows;
+        }
+    }
+    const size_t tables = (size_t)ntiles * n * (sizeof(BatchEnt) + 256) + (size_t)ntiles * sizeof(BatchTile) +
+                          nrows * sizeof(uint32_t) + (size_t)maxWx * 24 + 64 * 256;
+    return tables + std::min(v, std::max(budget, (size_t)1));
+}
+
+}  // namespace host
+}  // namespace tvs
+
 extern "C" {
 
 int tvs_batch_create(const tvs_tile *tiles, int32_t ntiles, int32_t n_sectors, uint32_t flags,

@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "../../include/libtvs.h"
 #include "tvs_geom.h"
 
 namespace tvs {
@@ -66,6 +67,22 @@ int total_on_stream(const float *d_dem, int H, int W, double dx, double h0, int 
                     uint32_t flags, hipStream_t st, size_t budget);
 // Device scratch that total_on_stream takes for these arguments.
 size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t flags, size_t budget);
+
+// Pinned host staging owned by a caller of batch_enqueue (grown there, freed by the owner).
+struct PinnedStaging {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+// Do the skewed rows of grids with sides up to maxWx fit the batched sweep's LDS?
+bool batch_rows_fit(int maxWx, bool f64);
+// Total viewsheds of independent tiles as one batch enqueued on `st` (no graph): per sector chunk
+// (skewed viewshed rows within `budget` bytes) one persistent fused relocate + sweep launch over
+// every (tile, sector, row) item and one back-projection launch over every tile. Flags: the
+// decision precision and slope form (TVS_FLAG_SLOPE_F32, _F64, _EXACT).
+int batch_enqueue(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, hipStream_t st, size_t budget,
+                  PinnedStaging &stage, int *out_chunks);
+// Device memory batch_enqueue takes for these tiles beyond their maps (an upper bound).
+size_t batch_scratch_bytes(const tvs_tile *tiles, int ntiles, int n, size_t budget);
 
 }  // namespace host
 }  // namespace tvs

@@ -2,9 +2,14 @@
 //
 // Grids are uploaded once and stay resident. Clients submit total-viewshed and singular
 // requests from any thread; one scheduler thread owns the device work:
-//  - total requests are admitted in arrival order while their device memory (output map plus
-//    the launch sequence's scratch) fits the HBM budget, each on the next of several streams,
-//    so requests that arrive while others run are started and overlap on the device;
+//  - total requests are admitted in arrival order while their device memory (output maps plus
+//    scratch) fits the HBM budget. Whenever one of two group slots is free, the waiting totals
+//    (same sector count and precision, up to a group limit) leave together as one batch: one
+//    persistent fused relocate + sweep launch over every (request, sector, skewed row) item and
+//    one back-projection launch per sector chunk, on the slot's stream; requests that arrive while
+//    both groups run gather into the next group. Totals the batched sweep does not take (float
+//    Kahan sums, the lane-per-target sweep, the full walk, rows longer than the LDS) run alone on
+//    the next of several streams, overlapping with the rest;
 //  - singular requests that are waiting are launched together: one multi-query ray-scan launch
 //    (every line of sight of every query, one wavefront each) and one per-query area sum, up to a
 //    batch limit, as soon as the previous singular batch has finished;
@@ -71,6 +76,16 @@ struct Request {
     int batch = -1;            // singular: its batch slot
 };
 
+// One launched group of total requests (a batch over their grids) and its pinned staging.
+struct TotGroup {
+    bool busy = false;
+    std::vector<Request *> reqs;
+    hipEvent_t ev = nullptr;
+    int stream = 0;     // index into the server's streams
+    PinnedStaging stage;
+    size_t bytes = 0;   // budget held: the maps and the batch's scratch
+};
+
 // One launched group of singular queries and its staging memory.
 struct SingBatch {
     bool busy = false;
@@ -94,6 +109,7 @@ struct tvs_server {
     size_t budget = 0, used = 0, peak = 0;
     int nstreams = 4;
     int max_batch = 64;
+    int max_total_batch = 16;
     std::vector<hipStream_t> streams;
     int next_stream = 0;
     hipStream_t sing_stream = nullptr;
@@ -105,7 +121,8 @@ struct tvs_server {
     std::unordered_map<uint64_t, Request *> reqs;
     uint64_t next_ticket = 1;
     SingBatch sb[2];
-    int64_t n_done = 0, n_batches = 0, n_batched = 0, max_running = 0;
+    TotGroup tg[2];
+    int64_t n_done = 0, n_batches = 0, n_batched = 0, max_running = 0, n_tbatches = 0, n_tbatched = 0;
     bool stop = false;
     int fatal = TVS_OK;
     std::thread worker;
@@ -118,7 +135,7 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 // Device memory of a total request: its map and the launch sequence's scratch (capped at a
 // quarter of the budget, so that several requests can run side by side).
 size_t total_bytes(const tvs_server *s, const Grid &g, const Request *r) {
-    const size_t cap = std::max(s->budget / 4, (size_t)64 << 20);
+    const size_t cap = std::max(s->budget / 4, (size_t)64 << 20);  // launch_cap
     return align256((size_t)g.rows * g.cols * sizeof(double)) +
            total_scratch_bytes(g.rows, g.cols, g.spacing, r->n, r->R, r->flags, cap);
 }
@@ -221,6 +238,59 @@ void finish(tvs_server *s, Request *r, int status) {
     s->n_done += 1;
 }
 
+// Scratch cap of one launch sequence: a quarter of the budget, so that several run side by side.
+size_t launch_cap(const tvs_server *s) { return std::max(s->budget / 4, (size_t)64 << 20); }
+
+// Total requests the batched sweep takes: the default early exit, double or float decisions, rows
+// that fit the LDS.
+bool batchable(const tvs_server *s, const Request *r) {
+    const uint32_t pmask = TVS_FLAG_SLOPE_F32 | TVS_FLAG_SLOPE_F64 | TVS_FLAG_SLOPE_EXACT;
+    if (r->flags & ~pmask) return false;
+    const Grid &g = s->grids[r->dem];
+    return batch_rows_fit(std::max(g.rows, g.cols), (r->flags & TVS_FLAG_SLOPE_F32) == 0);
+}
+
+tvs_tile tile_of(const tvs_server *s, const Request *r) {
+    const Grid &g = s->grids[r->dem];
+    tvs_tile t;
+    t.d_dem = g.d;
+    t.d_out = r->d_out;
+    t.rows = g.rows;
+    t.cols = g.cols;
+    t.spacing = g.spacing;
+    t.obs_height = r->h0;
+    t.max_dist = r->R;
+    return t;
+}
+
+// Launches the group's requests as one batch on the slot's stream (caller holds mu); the maps are
+// taken stream-ordered there.
+int launch_total_group(tvs_server *s, TotGroup &G) {
+    hipStream_t st = s->streams[G.stream];
+    std::vector<tvs_tile> tiles;
+    for (Request *r : G.reqs) {
+        const Grid &g = s->grids[r->dem];
+        r->state = ST_RUNNING;
+        r->t_start = Clock::now();
+        r->stream = G.stream;
+        if (hipMallocAsync((void **)&r->d_out, (size_t)g.rows * g.cols * sizeof(double), st) != hipSuccess) {
+            (void)hipGetLastError();
+            r->d_out = nullptr;
+            return fail(TVS_ENOMEM, "map of %d x %d not available", g.rows, g.cols);
+        }
+        tiles.push_back(tile_of(s, r));
+    }
+    int chunks = 0;
+    if (int rc = batch_enqueue(tiles.data(), (int)tiles.size(), G.reqs[0]->n, G.reqs[0]->flags, st, launch_cap(s),
+                               G.stage, &chunks))
+        return rc;
+    HIPCHK(hipEventRecord(G.ev, st));
+    G.busy = true;
+    s->n_tbatches += 1;
+    s->n_tbatched += (int64_t)G.reqs.size();
+    return TVS_OK;
+}
+
 void scheduler(tvs_server *s) {
     (void)hipSetDevice(s->dev);
     std::unique_lock<std::mutex> lk(s->mu);
@@ -240,6 +310,17 @@ void scheduler(tvs_server *s) {
             s->running.erase(s->running.begin() + x);
             progress = true;
         }
+        for (TotGroup &G : s->tg) {
+            if (!G.busy) continue;
+            const hipError_t q = hipEventQuery(G.ev);
+            if (q == hipErrorNotReady) continue;
+            for (Request *r : G.reqs) finish(s, r, q == hipSuccess ? TVS_OK : TVS_EDEVICE);
+            s->used -= G.bytes;
+            G.bytes = 0;
+            G.reqs.clear();
+            G.busy = false;
+            progress = true;
+        }
         for (SingBatch &b : s->sb) {
             if (!b.busy) continue;
             const hipError_t q = hipEventQuery(b.ev);
@@ -254,14 +335,53 @@ void scheduler(tvs_server *s) {
         }
         if (progress) s->cv_done.notify_all();
         if (s->stop && s->q_total.empty() && s->q_sing.empty() && s->running.empty() && !s->sb[0].busy &&
-            !s->sb[1].busy)
+            !s->sb[1].busy && !s->tg[0].busy && !s->tg[1].busy)
             break;
         // admission of total requests, in arrival order
         while (!s->q_total.empty()) {
             Request *r = s->q_total.front();
+            const bool idle = s->running.empty() && !s->tg[0].busy && !s->tg[1].busy;
+            if (batchable(s, r)) {
+                // a free group slot takes the waiting totals of the front request's sector count and
+                // precision, in arrival order, while their maps and the batch's scratch fit the budget
+                TotGroup *G = !s->tg[0].busy ? &s->tg[0] : !s->tg[1].busy ? &s->tg[1] : nullptr;
+                if (!G) break;  // both groups run: arrivals gather into the next one
+                std::vector<tvs_tile> tiles;
+                size_t maps = 0, need = 0;
+                auto it = s->q_total.begin();
+                while (it != s->q_total.end() && (int)G->reqs.size() < s->max_total_batch) {
+                    Request *x = *it;
+                    if (!batchable(s, x) || x->n != r->n || x->flags != r->flags) break;
+                    const Grid &gx = s->grids[x->dem];
+                    tiles.push_back(tile_of(s, x));
+                    const size_t mx = maps + align256((size_t)gx.rows * gx.cols * sizeof(double));
+                    const size_t nx = mx + batch_scratch_bytes(tiles.data(), (int)tiles.size(), x->n, launch_cap(s));
+                    if ((!G->reqs.empty() || !idle) && s->used + nx > s->budget) break;  // wait for memory
+                    maps = mx;
+                    need = nx;
+                    G->reqs.push_back(x);
+                    it = s->q_total.erase(it);
+                }
+                if (G->reqs.empty()) break;
+                const int rc = launch_total_group(s, *G);
+                if (rc != TVS_OK) {
+                    for (Request *x : G->reqs) finish(s, x, rc);
+                    G->reqs.clear();
+                    G->busy = false;
+                    progress = true;
+                    continue;
+                }
+                G->bytes = need;
+                s->used += need;
+                s->peak = std::max(s->peak, s->used);
+                const int64_t nrun = (int64_t)(s->running.size() + s->tg[0].reqs.size() + s->tg[1].reqs.size());
+                s->max_running = std::max(s->max_running, nrun);
+                progress = true;
+                continue;
+            }
             const Grid &g = s->grids[r->dem];
             const size_t need = total_bytes(s, g, r);
-            if (!s->running.empty() && s->used + need > s->budget) break;  // wait for memory
+            if (!idle && s->used + need > s->budget) break;  // wait for memory
             s->q_total.pop_front();
             const int si = s->next_stream;
             s->next_stream = (s->next_stream + 1) % s->nstreams;
@@ -277,7 +397,7 @@ void scheduler(tvs_server *s) {
             }
             if (rc == TVS_OK)
                 rc = total_on_stream(g.d, g.rows, g.cols, g.spacing, r->h0, r->n, r->R, r->d_out, r->flags, st,
-                                     std::max(s->budget / 4, (size_t)64 << 20));
+                                     launch_cap(s));
             if (rc == TVS_OK && hipEventRecord(r->ev, st) != hipSuccess) rc = TVS_EDEVICE;
             if (rc != TVS_OK) {
                 finish(s, r, rc);
@@ -288,7 +408,8 @@ void scheduler(tvs_server *s) {
             s->used += need;
             s->peak = std::max(s->peak, s->used);
             s->running.push_back(r);
-            s->max_running = std::max<int64_t>(s->max_running, (int64_t)s->running.size());
+            const int64_t nrun = (int64_t)(s->running.size() + s->tg[0].reqs.size() + s->tg[1].reqs.size());
+            s->max_running = std::max(s->max_running, nrun);
             progress = true;
         }
         // singular queries that are waiting: up to two batches in flight (double-buffered
@@ -309,7 +430,7 @@ void scheduler(tvs_server *s) {
             s->cv_done.notify_all();
             continue;
         }
-        const bool busy = !s->running.empty() || s->sb[0].busy || s->sb[1].busy;
+        const bool busy = !s->running.empty() || s->sb[0].busy || s->sb[1].busy || s->tg[0].busy || s->tg[1].busy;
         // poll device work every 50 us; sleep until a submission when idle
         s->cv_work.wait_for(lk, busy ? std::chrono::microseconds(50) : std::chrono::milliseconds(50));
     }
@@ -339,8 +460,10 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
     if (!out) return fail(TVS_EINVAL, "null out");
     tvs_server_config c{};
     if (cfg) c = *cfg;
-    if (c.streams < 0 || c.streams > 16 || c.max_singular_batch < 0 || c.hbm_budget_bytes < 0)
-        return fail(TVS_EINVAL, "streams in [0, 16], max_singular_batch >= 0, hbm_budget_bytes >= 0");
+    if (c.streams < 0 || c.streams > 16 || c.max_singular_batch < 0 || c.hbm_budget_bytes < 0 ||
+        c.max_total_batch < 0)
+        return fail(TVS_EINVAL,
+                    "streams in [0, 16], max_singular_batch >= 0, max_total_batch >= 0, hbm_budget_bytes >= 0");
     tvs_server *s = new (std::nothrow) tvs_server;
     if (!s) return fail(TVS_ENOMEM, "host memory for the server");
     auto bail = [&](int rc) {
@@ -348,6 +471,8 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
         if (s->sing_stream) (void)hipStreamDestroy(s->sing_stream);
         for (SingBatch &b : s->sb)
             if (b.ev) (void)hipEventDestroy(b.ev);
+        for (TotGroup &G : s->tg)
+            if (G.ev) (void)hipEventDestroy(G.ev);
         delete s;
         return rc;
     };
@@ -357,6 +482,7 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
     s->budget = c.hbm_budget_bytes > 0 ? (size_t)c.hbm_budget_bytes : freeb / 2;
     s->nstreams = c.streams > 0 ? c.streams : 4;
     s->max_batch = c.max_singular_batch > 0 ? c.max_singular_batch : 64;
+    s->max_total_batch = c.max_total_batch > 0 ? c.max_total_batch : 16;
     pool_keep_memory(s->dev);
     for (int x = 0; x < s->nstreams; ++x) {
         hipStream_t st;
@@ -369,6 +495,12 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
     for (SingBatch &b : s->sb)
         if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess)
             return bail(fail(TVS_EDEVICE, "event creation failed"));
+    for (int x = 0; x < 2; ++x) {
+        TotGroup &G = s->tg[x];
+        G.stream = x % s->nstreams;
+        if (hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess)
+            return bail(fail(TVS_EDEVICE, "event creation failed"));
+    }
     s->worker = std::thread(scheduler, s);
     *out = s;
     return TVS_OK;
@@ -530,7 +662,8 @@ int tvs_server_get_stats(tvs_server *s, tvs_server_stats *st) {
     memset(st, 0, sizeof(*st));
     st->grids = (int32_t)s->grids.size();
     st->pending = (int32_t)(s->q_total.size() + s->q_sing.size());
-    st->running = (int32_t)s->running.size() + (int32_t)(s->sb[0].reqs.size() + s->sb[1].reqs.size());
+    st->running = (int32_t)s->running.size() + (int32_t)(s->sb[0].reqs.size() + s->sb[1].reqs.size()) +
+                  (int32_t)(s->tg[0].reqs.size() + s->tg[1].reqs.size());
     st->completed = s->n_done;
     st->singular_batches = s->n_batches;
     st->singular_batched = s->n_batched;
@@ -538,6 +671,8 @@ int tvs_server_get_stats(tvs_server *s, tvs_server_stats *st) {
     st->budget_bytes = (int64_t)s->budget;
     st->bytes_in_use = (int64_t)s->used;
     st->peak_bytes = (int64_t)s->peak;
+    st->total_batches = s->n_tbatches;
+    st->total_batched = s->n_tbatched;
     return TVS_OK;
 }
 
@@ -556,6 +691,10 @@ int tvs_server_destroy(tvs_server *s) {
         if (r->d_out) (void)hipFreeAsync(r->d_out, s->streams[std::max(r->stream, 0)]);
         if (r->ev) (void)hipEventDestroy(r->ev);
         delete r;
+    }
+    for (TotGroup &G : s->tg) {
+        if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.stage.p) (void)hipHostFree(G.stage.p);
     }
     for (SingBatch &b : s->sb) {
         if (b.ev) (void)hipEventDestroy(b.ev);

@@ -183,15 +183,27 @@ BATCH64 = dict(ntiles=64, seed=4, side_lo=256, side_hi=2048, roughness=0.55, zma
                h_lo=1.5, h_hi=30.0, n_sectors=180)
 
 
-def batch_workload(ntiles: int = 64, seed: int = 4, side_lo: int = 256, side_hi: int = 2048) -> list:
-    """List of dicts (dem, spacing, obs_height, max_dist) for a batch of tiles."""
+def _batch_tile(args):
+    side, i = args
+    return fractal_dem(side, 4000 + i, BATCH64["roughness"], BATCH64["zmax"])
+
+
+def batch_workload(ntiles: int = 64, seed: int = 4, side_lo: int = 256, side_hi: int = 2048,
+                   workers: int = 1) -> list:
+    """List of dicts (dem, spacing, obs_height, max_dist) for a batch of tiles. Each tile's terrain
+    depends only on its index, so ``workers`` > 1 generates them in that many processes with the
+    same result."""
     w = BATCH64
     rng = np.random.default_rng(seed)
     sides = rng.integers(side_lo, side_hi + 1, ntiles)
     heights = rng.uniform(w["h_lo"], w["h_hi"], ntiles)
-    out = []
-    for i in range(ntiles):
-        side = int(sides[i])
-        out.append(dict(dem=fractal_dem(side, 4000 + i, w["roughness"], w["zmax"]), spacing=w["spacing"],
-                        obs_height=float(heights[i]), max_dist=side * w["spacing"]))
-    return out
+    jobs = [(int(sides[i]), i) for i in range(ntiles)]
+    if workers > 1:
+        from concurrent.futures import ProcessPoolExecutor
+
+        with ProcessPoolExecutor(max_workers=workers) as ex:
+            dems = list(ex.map(_batch_tile, jobs))
+    else:
+        dems = [_batch_tile(j) for j in jobs]
+    return [dict(dem=dems[i], spacing=w["spacing"], obs_height=float(heights[i]),
+                 max_dist=int(sides[i]) * w["spacing"]) for i in range(ntiles)]

@@ -133,6 +133,30 @@ def test_singular_queries_are_batched_and_match_oracle(tvs, orc):
     srv.close()
 
 
+def test_total_requests_share_launches(tvs):
+    """Totals queued together leave in groups: one batched launch sequence over several requests'
+    grids (their sector count and flags shared), while float Kahan totals run alone; every map equals
+    the request computed alone, bit for bit."""
+    dems = _grids()
+    srv = tvs.Server(streams=4, max_total_batch=8)
+    ids = [srv.add_grid(d, GRIDS[x][2]) for x, d in enumerate(dems)]
+    rng = np.random.default_rng(11)
+    reqs = []
+    for x in range(30):
+        g = int(rng.integers(0, len(GRIDS)))
+        H, W, dx = GRIDS[g]
+        flags = 0x4 if x % 10 == 3 else (0x40 if x % 7 == 5 else 0)
+        reqs.append(("t", g, float(rng.uniform(1.5, 30.0)), 24, float(rng.choice([math.inf, max(H, W) * dx])), flags))
+    note("server total flood")
+    tickets = [_submit(srv, ids, r) for r in reqs]
+    _check_all(tvs, srv, dems, reqs, tickets)
+    st = srv.stats()
+    print(f"total flood: {st.total_batches} groups for {st.total_batched} requests", flush=True)
+    assert st.total_batched == sum(1 for r in reqs if r[5] != 0x4)
+    assert st.total_batches < st.total_batched
+    srv.close()
+
+
 def test_server_rejects_bad_requests(tvs):
     srv = tvs.Server()
     gid = srv.add_grid(np.zeros((8, 9), np.float32), 10.0)
