@@ -83,6 +83,9 @@ struct tvs_batch {
     bool f64 = true, rcp = true, count = false;
     std::vector<tvs_tile> tiles;
     std::vector<std::vector<Sector>> sectors;  // per tile
+    std::vector<const float *> demT;           // per tile: its transposed grid (empty: none)
+    bool transpose = false;                    // the pass transposes the tiles into demT first
+    bool persistent = true;                    // persistent sweep (else one workgroup per item)
     std::vector<ChunkPlan> chunks;
     int maxWx = 0, tabN = 0, maxK = 0;
     bool counted = false;
@@ -204,6 +207,7 @@ void build_tables(tvs_batch *b, std::vector<BatchEnt> &ent, std::vector<BatchTil
                 e.s.wrap = s.wrap;
                 e.s.winv = s.wrap ? 1.0f / (float)s.wrap : 0.0f;
                 e.dem = T.d_dem;
+                e.demT = b->demT.empty() ? nullptr : b->demT[t];
                 e.H = T.rows;
                 e.W = T.cols;
                 e.pitch = pitch;
@@ -239,13 +243,21 @@ hipError_t enqueue_pass(tvs_batch *b, hipStream_t st) {
     if ((e = launch_divtab(b->tab32, b->tab64, b->tabN, st)) != hipSuccess) return e;
     if ((e = launch_fill_u32(b->counters, (int64_t)b->chunks.size(), 0u, st)) != hipSuccess) return e;
     b->launches = 2;
+    if (b->transpose)
+        for (int t = 0; t < b->ntiles; ++t) {
+            const tvs_tile &T = b->tiles[t];
+            if ((e = launch_transpose(T.d_dem, const_cast<float *>(b->demT[t]), T.rows, T.cols, st)) != hipSuccess)
+                return e;
+            ++b->launches;
+        }
     if (b->count) {
         if ((e = launch_fill_u32((uint32_t *)b->work, 128, 0u, st)) != hipSuccess) return e;
         ++b->launches;
     }
     for (size_t ci = 0; ci < b->chunks.size(); ++ci) {
         const ChunkPlan &c = b->chunks[ci];
-        if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + c.item_off, c.nitems, b->counters + ci, b->V,
+        if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + c.item_off, c.nitems,
+                                    b->persistent ? b->counters + ci : nullptr, b->V,
                                     b->tab32, b->tab64, b->f64, b->rcp, b->shape.waves, b->grid, b->maxWx,
                                     b->maxK, b->count ? b->work : nullptr, st)) != hipSuccess)
             return e;
@@ -354,7 +366,10 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     const size_t sz_ent = align256(ent.size() * sizeof(BatchEnt));
     const size_t sz_bt = align256(bt.size() * sizeof(BatchTile));
     const size_t sz_items = align256(items.size() * sizeof(uint32_t));
-    b->dbytes = sz_tab32 + sz_tab64 + sz_ctr + sz_work + sz_ent + sz_bt + sz_items + align256(maxV);
+    size_t sz_demT = 0;
+    if (n >= 2)  // sectors of the 45..135 deg axes read the tiles' transposed grids
+        for (int t = 0; t < ntiles; ++t) sz_demT += align256((size_t)tiles[t].rows * tiles[t].cols * sizeof(float));
+    b->dbytes = sz_tab32 + sz_tab64 + sz_ctr + sz_work + sz_ent + sz_bt + sz_items + sz_demT + align256(maxV);
     if (hipMalloc((void **)&b->dmem, b->dbytes) != hipSuccess) {
         (void)hipGetLastError();
         b->dmem = nullptr;
@@ -368,6 +383,16 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     b->ent = (BatchEnt *)p; p += sz_ent;
     b->btiles = (BatchTile *)p; p += sz_bt;
     b->items = (uint32_t *)p; p += sz_items;
+    if (sz_demT) {
+        b->transpose = true;
+        for (int t = 0; t < ntiles; ++t) {
+            b->demT.push_back((const float *)p);
+            p += align256((size_t)tiles[t].rows * tiles[t].cols * sizeof(float));
+        }
+        for (const ChunkPlan &c : b->chunks)  // tile t's sectors of chunk c follow its ent_off + t * nsec
+            for (int t = 0; t < ntiles; ++t)
+                for (int x = 0; x < c.k1 - c.k0; ++x) ent[c.ent_off + (size_t)t * (c.k1 - c.k0) + x].demT = b->demT[t];
+    }
     b->V = (uint32_t *)p;
     HIPCHK(hipMemcpy(b->ent, ent.data(), ent.size() * sizeof(BatchEnt), hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(b->btiles, bt.data(), bt.size() * sizeof(BatchTile), hipMemcpyHostToDevice));
@@ -417,9 +442,11 @@ bool batch_rows_fit(int maxWx, bool f64) {
 // the same plan, work lists and launches as a captured batch pass. The work lists go through the
 // caller's pinned staging buffer (grown here; the caller keeps it untouched until the stream has
 // passed this work), the device memory is taken and returned stream-ordered on `st`.
-int batch_enqueue(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, hipStream_t st, size_t budget,
-                  PinnedStaging &stage, int *out_chunks) {
+int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, int n, uint32_t flags, hipStream_t st,
+                  size_t budget, PinnedStaging &stage, int *out_chunks) {
     tvs_batch b;
+    b.persistent = false;  // other work (the server's singular launches) interleaves with its workgroups
+    if (demT) b.demT.assign(demT, demT + ntiles);
     b.ntiles = ntiles;
     b.n = n;
     b.flags = flags;
@@ -498,23 +525,25 @@ int batch_enqueue(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, hipS
     return TVS_OK;
 }
 
-// Device memory batch_enqueue takes for these tiles (beyond their maps), an upper bound.
-size_t batch_scratch_bytes(const tvs_tile *tiles, int ntiles, int n, size_t budget) {
-    int maxWx = 0;
-    size_t v = 0, nrows = 0;
-    for (int t = 0; t < ntiles; ++t) {
-        const tvs_tile &T = tiles[t];
-        maxWx = std::max(maxWx, std::max(T.rows, T.cols));
-        const int pitch = pitch_of(T.rows, T.cols);
-        for (int k = 0; k < n; ++k) {
-            const Sector s = plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist);
-            v += (size_t)s.prows * pitch * 4;
-            nrows += (size_t)s.nrows;
-        }
+// One tile's share of batch_enqueue's device memory: its skewed viewshed rows over all sectors and its
+// work items and entries.
+BatchSize batch_tile_size(const tvs_tile &T, int n) {
+    BatchSize z;
+    z.maxWx = std::max(T.rows, T.cols);
+    const int pitch = pitch_of(T.rows, T.cols);
+    size_t nrows = 0;
+    for (int k = 0; k < n; ++k) {
+        const Sector s = plan_sector(k, n, T.rows, T.cols, T.spacing, T.max_dist);
+        z.vbytes += (size_t)s.prows * pitch * 4;
+        nrows += (size_t)s.nrows;
     }
-    const size_t tables = (size_t)ntiles * n * (sizeof(BatchEnt) + 256) + (size_t)ntiles * sizeof(BatchTile) +
-                          nrows * sizeof(uint32_t) + (size_t)maxWx * 24 + 64 * 256;
-    return tables + std::min(v, std::max(budget, (size_t)1));
+    z.tables = (size_t)n * (sizeof(BatchEnt) + 256) + sizeof(BatchTile) + nrows * sizeof(uint32_t);
+    return z;
+}
+
+// Device memory batch_enqueue takes for tiles of these summed sizes (beyond their maps), an upper bound.
+size_t batch_scratch_bytes(const BatchSize &sum, size_t budget) {
+    return sum.tables + (size_t)sum.maxWx * 24 + 64 * 256 + std::min(sum.vbytes, std::max(budget, (size_t)1));
 }
 
 }  // namespace host

@@ -76,13 +76,26 @@ struct PinnedStaging {
 // Do the skewed rows of grids with sides up to maxWx fit the batched sweep's LDS?
 bool batch_rows_fit(int maxWx, bool f64);
 // Total viewsheds of independent tiles as one batch enqueued on `st` (no graph): per sector chunk
-// (skewed viewshed rows within `budget` bytes) one persistent fused relocate + sweep launch over
-// every (tile, sector, row) item and one back-projection launch over every tile. Flags: the
-// decision precision and slope form (TVS_FLAG_SLOPE_F32, _F64, _EXACT).
-int batch_enqueue(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, hipStream_t st, size_t budget,
-                  PinnedStaging &stage, int *out_chunks);
-// Device memory batch_enqueue takes for these tiles beyond their maps (an upper bound).
-size_t batch_scratch_bytes(const tvs_tile *tiles, int ntiles, int n, size_t budget);
+// (skewed viewshed rows within `budget` bytes) one fused relocate + sweep launch with a workgroup per
+// (tile, sector, row) item and one back-projection launch over every tile. `demT` (nullable) holds
+// each tile's transposed grid, read for the 45..135 deg axes. Flags: the decision precision and slope
+// form (TVS_FLAG_SLOPE_F32, _F64, _EXACT).
+int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, int n, uint32_t flags, hipStream_t st,
+                  size_t budget, PinnedStaging &stage, int *out_chunks);
+// Sizes that add up over the tiles of a batch.
+struct BatchSize {
+    size_t vbytes = 0;  // skewed viewshed rows of every sector
+    size_t tables = 0;  // entries, tiles and work items
+    int maxWx = 0;      // longest side
+    void add(const BatchSize &o) {
+        vbytes += o.vbytes;
+        tables += o.tables;
+        maxWx = maxWx > o.maxWx ? maxWx : o.maxWx;
+    }
+};
+BatchSize batch_tile_size(const tvs_tile &T, int n);
+// Device memory batch_enqueue takes for tiles of these summed sizes beyond their maps (an upper bound).
+size_t batch_scratch_bytes(const BatchSize &sum, size_t budget);
 
 }  // namespace host
 }  // namespace tvs

@@ -50,6 +50,7 @@ static_assert(sizeof(ChunkArgs) <= 4096, "chunk parameters must fit the kernel a
 struct BatchEnt {
     SecDev s;
     const float *dem;  // the tile's DEM (device)
+    const float *demT; // its transpose (W x H), or null: the 45..135 deg axes read the DEM by columns
     int32_t H, W;      // tile dims
     int32_t pitch;     // row pitch of this tile's skewed rows
     float h0f;         // observer height rounded to float
@@ -105,9 +106,9 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
 hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first,
                                hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
-// Batched path: a persistent fused relocate + sweep over a chunk's (tile, sector, row) items,
-// then one back-projection launch over every tile of the chunk. launch_sweep_batch with
-// grid == 0 only prepares the kernel's LDS limit.
+// Batched path: a fused relocate + sweep over a chunk's (tile, sector, row) items (persistent with a
+// counter, else one workgroup per item), then one back-projection launch over every tile of the
+// chunk. launch_sweep_batch with grid == 0 only prepares the kernel's LDS limit.
 hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, int maxK, unsigned long long *work,

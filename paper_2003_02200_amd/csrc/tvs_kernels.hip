@@ -921,9 +921,11 @@ template <typename Tz> __device__ __forceinline__ Tz h0_of(const BatchEnt &e);
 template <> __device__ __forceinline__ float h0_of<float>(const BatchEnt &e) { return e.h0f; }
 template <> __device__ __forceinline__ double h0_of<double>(const BatchEnt &e) { return e.h0; }
 
-// Persistent sweep over every (tile, sector, skewed row) item of a batch chunk: each workgroup
-// takes the next item from a device counter until the list is exhausted (every workgroup
-// reaches the end, the counter only grows), gathers the row from its tile's DEM and sweeps it.
+// Sweep over every (tile, sector, skewed row) item of a batch chunk. Persistent (counter non-null):
+// each workgroup takes the next item from a device counter until the list is exhausted (every
+// workgroup reaches the end, the counter only grows). Otherwise workgroup b takes item b (one launch
+// of nitems workgroups, which other kernels' workgroups interleave with). Each row is gathered from
+// its tile's DEM (or the tile's transposed copy for the 45..135 deg axes) and swept.
 template <typename Tz, int NW, bool RCP, int SLIDE = 0>
 __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restrict__ ent,
                                                          const uint32_t *__restrict__ items, int nitems,
@@ -936,11 +938,17 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
     __shared__ unsigned long long wg_work;
     if (work && threadIdx.x == 0) wg_work = 0;
     unsigned long long evals = 0;
-    for (;;) {
-        if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
-        __syncthreads();
-        const int it = __builtin_amdgcn_readfirstlane(next);
-        __syncthreads();  // every thread has read `next` before thread 0 writes it again
+    for (int pass = 0;; ++pass) {
+        int it;
+        if (counter) {
+            if (threadIdx.x == 0) next = (int)atomicAdd(counter, 1u);
+            __syncthreads();
+            it = __builtin_amdgcn_readfirstlane(next);
+            __syncthreads();  // every thread has read `next` before thread 0 writes it again
+        } else {
+            if (pass) break;
+            it = (int)blockIdx.x;
+        }
         if (it >= nitems) break;
         const uint32_t item = items[it];
         const BatchEnt &E = ent[item >> 16];
@@ -948,7 +956,7 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         int jlo;
         int Hx, Wx;
         frame_dims(E.s.kase, E.H, E.W, Hx, Wx);
-        const int nt = gather_row<Tz>(frame_ref(E.s.kase, E.H, E.W, E.dem, nullptr), Hx, Wx, E.s, ri, row, jlo);
+        const int nt = gather_row<Tz>(frame_ref(E.s.kase, E.H, E.W, E.dem, E.demT), Hx, Wx, E.s, ri, row, jlo);
         if (nt > 0)
             evals += sweep_row<Tz, NW, RCP, true, SLIDE>(row, nt, E.s.K, h0_of<Tz>(E), tab,
                                                          V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
@@ -1618,7 +1626,8 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
     return hipGetLastError();
 }
 
-// With grid == 0 only the kernel's LDS limit is raised (outside any graph capture).
+// With grid == 0 only the kernel's LDS limit is raised (outside any graph capture). Without a
+// counter the launch has one workgroup per item (grid is ignored).
 hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int nitems, unsigned int *counter,
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, int maxK, unsigned long long *work,
@@ -1630,7 +1639,7 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
     do {                                                                                                \
         auto f = k_sweep_batch<TZ, NW, RCP, SL>;                                                        \
         if (grid == 0) return set_lds(f, lds);                                                          \
-        f<<<grid, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work, rmq);                  \
+        f<<<counter ? grid : nitems, 64 * NW, lds, st>>>(ent, items, nitems, counter, V, TAB, work, rmq); \
     } while (0)
 #define TVS_BATCH_NW(NW)                                                                                \
     do {                                                                                                \

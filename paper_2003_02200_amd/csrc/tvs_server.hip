@@ -50,6 +50,7 @@ double ms_since(Clock::time_point a, Clock::time_point b) {
 
 struct Grid {
     float *d = nullptr;
+    float *dT = nullptr;  // its transpose (cols x rows): batched sweeps read it for the 45..135 deg axes
     int rows = 0, cols = 0;
     double spacing = 0.0;
 };
@@ -268,6 +269,7 @@ tvs_tile tile_of(const tvs_server *s, const Request *r) {
 int launch_total_group(tvs_server *s, TotGroup &G) {
     hipStream_t st = s->streams[G.stream];
     std::vector<tvs_tile> tiles;
+    std::vector<const float *> demT;
     for (Request *r : G.reqs) {
         const Grid &g = s->grids[r->dem];
         r->state = ST_RUNNING;
@@ -279,10 +281,11 @@ int launch_total_group(tvs_server *s, TotGroup &G) {
             return fail(TVS_ENOMEM, "map of %d x %d not available", g.rows, g.cols);
         }
         tiles.push_back(tile_of(s, r));
+        demT.push_back(g.dT);
     }
     int chunks = 0;
-    if (int rc = batch_enqueue(tiles.data(), (int)tiles.size(), G.reqs[0]->n, G.reqs[0]->flags, st, launch_cap(s),
-                               G.stage, &chunks))
+    if (int rc = batch_enqueue(tiles.data(), demT.data(), (int)tiles.size(), G.reqs[0]->n, G.reqs[0]->flags, st,
+                               launch_cap(s), G.stage, &chunks))
         return rc;
     HIPCHK(hipEventRecord(G.ev, st));
     G.busy = true;
@@ -346,17 +349,19 @@ void scheduler(tvs_server *s) {
                 // precision, in arrival order, while their maps and the batch's scratch fit the budget
                 TotGroup *G = !s->tg[0].busy ? &s->tg[0] : !s->tg[1].busy ? &s->tg[1] : nullptr;
                 if (!G) break;  // both groups run: arrivals gather into the next one
-                std::vector<tvs_tile> tiles;
+                BatchSize sum;
                 size_t maps = 0, need = 0;
                 auto it = s->q_total.begin();
                 while (it != s->q_total.end() && (int)G->reqs.size() < s->max_total_batch) {
                     Request *x = *it;
                     if (!batchable(s, x) || x->n != r->n || x->flags != r->flags) break;
                     const Grid &gx = s->grids[x->dem];
-                    tiles.push_back(tile_of(s, x));
+                    BatchSize with = sum;
+                    with.add(batch_tile_size(tile_of(s, x), x->n));
                     const size_t mx = maps + align256((size_t)gx.rows * gx.cols * sizeof(double));
-                    const size_t nx = mx + batch_scratch_bytes(tiles.data(), (int)tiles.size(), x->n, launch_cap(s));
+                    const size_t nx = mx + batch_scratch_bytes(with, launch_cap(s));
                     if ((!G->reqs.empty() || !idle) && s->used + nx > s->budget) break;  // wait for memory
+                    sum = with;
                     maps = mx;
                     need = nx;
                     G->reqs.push_back(x);
@@ -524,6 +529,16 @@ int tvs_server_add_grid(tvs_server *s, const float *dem, int32_t rows, int32_t c
     if (hipMemcpy(g.d, dem, bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(g.d);
         return fail(TVS_EDEVICE, "grid upload failed");
+    }
+    if (hipMalloc((void **)&g.dT, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFree(g.d);
+        return fail(TVS_ENOMEM, "transposed grid of %d x %d not available", cols, rows);
+    }
+    if (launch_transpose(g.d, g.dT, rows, cols, nullptr) != hipSuccess || hipStreamSynchronize(nullptr) != hipSuccess) {
+        (void)hipFree(g.d);
+        (void)hipFree(g.dT);
+        return fail(TVS_EDEVICE, "grid transposition failed");
     }
     std::lock_guard<std::mutex> lk(s->mu);
     *out_id = (int32_t)s->grids.size();
@@ -703,7 +718,10 @@ int tvs_server_destroy(tvs_server *s) {
         if (b.h_area) (void)hipHostFree(b.h_area);
         if (b.d_mem) (void)hipFree(b.d_mem);
     }
-    for (Grid &g : s->grids) (void)hipFree(g.d);
+    for (Grid &g : s->grids) {
+        (void)hipFree(g.d);
+        (void)hipFree(g.dT);
+    }
     for (hipStream_t st : s->streams) {
         (void)hipStreamSynchronize(st);
         (void)hipStreamDestroy(st);

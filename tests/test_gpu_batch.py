@@ -81,7 +81,8 @@ def test_batch_equals_per_tile_and_oracle(tvs, orc, flags, prec):
             o.fill_(3.0)
         torch.cuda.synchronize()
     inf = b.info()
-    assert inf.tiles == len(TILES) and inf.chunks >= 1 and inf.kernel_launches == 2 + 2 * inf.chunks
+    # tables and counters, the tiles transposed (n >= 2), one sweep and one back-projection per chunk
+    assert inf.tiles == len(TILES) and inf.chunks >= 1 and inf.kernel_launches == 2 + len(TILES) + 2 * inf.chunks
     ev = sum(tvs.los_evals(H, W, dx, n, R)[0] for (H, W, dx, h0, R) in TILES)
     assert inf.los_evals == ev
     b.close()
