@@ -503,13 +503,14 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     uint32_t bits = 0;
     int m = 1;
     bool stop = false;
+    bool test = true;  // after a block in which half the lanes saw a target the next is not tested
     skipped = 0;
     for (; m + 31 <= mfull; m += 32) {
         if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads on the scalar path
         // The exit test passing implies the skip test passing (its blocks lie inside the exit's
         // range and its steps inside the remaining ones), so the exit is tested only for blocks
         // that can be skipped; a block that must be evaluated costs one test.
-        if (PRUNE && m > 1 && (!rmq || block_hidden(m))) {
+        if (PRUNE && m > 1 && (!rmq || (test && block_hidden(m)))) {
             if (hidden_from(m)) {
                 stop = true;
                 break;
@@ -525,7 +526,9 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         for (int s = 0; s < 32; ++s) vis_step(slope<RCP>(sub_rn(zp[DIR * (m + s)], h), t[s]), mx, bits);
         // 32 steps have shifted every earlier bit out: `bits` is this block's. Far from the POVs
         // most blocks see nothing on any lane, and skip the ring sums.
-        if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
+        const unsigned long long seen = __builtin_amdgcn_ballot_w64(bits != 0u);
+        if (seen) ra.add(bits, m);
+        test = __popcll(seen) < 32;  // skipping a test only evaluates a block it might have skipped
     }
     if (PRUNE && !stop && m > 1 && m <= mb) stop = hidden_from(m);
     uint32_t acc = ra.total();
