@@ -423,9 +423,9 @@ def bench_batch(args, ntiles, steps, warmup, standalone=False):
                    "los_evals_per_pass": evals, "flags": flags},
         "per_tile_loop": {"ms_per_pass": loop_s * 1e3, "value": evals / loop_s},
         "speedup_vs_per_tile_loop": loop_s / batch_s,
-        "plan": {"chunks": info.chunks, "graph_kernels": info.kernel_launches, "waves_per_group": info.waves_per_group,
-                 "groups": info.groups, "tuned": bool(info.tuned), "tune_ms": info.tune_ms,
-                 "create_s": create_s, "scratch_bytes": info.scratch_bytes},
+        "plan": {"chunks": info.chunks, "graph_kernels": info.kernel_launches, "tuned": bool(info.tuned),
+                 "tune_ms": info.tune_ms, "create_s": create_s, "scratch_bytes": info.scratch_bytes,
+                 "buckets": batch.buckets()},
         "max_rel_diff_vs_per_tile_loop": worst,
     }
     batch.close()

@@ -80,9 +80,13 @@ enum tvs_status {
 #define TVS_FLAG_SLOPE_F32 0x40u  /* float elevations and float decision (the paper's precision);
                                      with TVS_FLAG_SLOPE_EXACT the float quotient. Excludes
                                      TVS_FLAG_SLOPE_F64 */
-#define TVS_FLAG_AUTOTUNE 0x80u   /* batches only: time the candidate launch shapes on a sample of
-                                     the batch before building it and keep the fastest for batches
-                                     of the same size class (process-wide) */
+#define TVS_FLAG_AUTOTUNE 0x80u   /* batches: time the candidate launch shapes of each bucket of tiles
+                                     on a sample of its rows before building the batch; total viewshed:
+                                     time the sweep's waves per workgroup on a few sectors first. The
+                                     fastest shape is kept per size class, device and library build
+                                     (in memory and in a cache file: TVS_TUNE_CACHE, else
+                                     $XDG_CACHE_HOME/libtvs or ~/.cache/libtvs), and later calls
+                                     without the flag use it. Results are the same with any shape. */
 #define TVS_FLAG_RELOCATE 0x200u  /* total viewshed: run the relocation as its own kernel that writes every
                                      sector's skewed elevations (skwDEM) to device memory, and sweep from
                                      there (Section 4.2's first kernel); by default each sweep workgroup
@@ -225,7 +229,24 @@ typedef struct tvs_batch_info {
                                  (TVS_FLAG_COUNT_EVALS), else 0 */
     int64_t scratch_bytes;    /* device memory owned by the batch */
     double tune_ms;           /* time spent timing candidates at creation */
+    int32_t buckets;          /* groups of tiles with their own sweep launch and shape (tvs_batch_get_bucket) */
+    int32_t pad;
 } tvs_batch_info;
+
+/* A bucket of a batch: the tiles whose longest side and longest line of sight (capped at the side)
+ * fall in the same power-of-two classes; per sector chunk one sweep launch over their items, with
+ * its own launch shape. */
+typedef struct tvs_batch_bucket {
+    int32_t side_class;       /* ceil(log2(longest side)) */
+    int32_t reach_class;      /* ceil(log2(longest line of sight + 1)) */
+    int32_t tiles;
+    int32_t longest_side;
+    int32_t longest_reach;    /* target steps of the longest line of sight */
+    int32_t waves_per_group;  /* wavefronts per sweep workgroup */
+    int32_t groups_per_cu;    /* persistent workgroups per CU; 0: one workgroup per skewed row */
+    int32_t tuned;            /* 1 if the shape came from timing (now or remembered) */
+    int64_t items;            /* (tile, sector, skewed row) items over all chunks */
+} tvs_batch_bucket;
 
 /* Plans a batch: validates every tile, groups the sectors into chunks within the scratch budget,
  * uploads the work lists and captures one pass (per chunk: one persistent fused relocate + sweep
@@ -244,6 +265,9 @@ int tvs_batch_run(tvs_batch *batch, void *hip_stream);
 
 /* Plan, launch shape and counts of a batch (sweep_evals_done needs the last pass finished). */
 int tvs_batch_get_info(const tvs_batch *batch, tvs_batch_info *info);
+
+/* Bucket i (0 <= i < info.buckets) of a batch; bucket 0 holds the largest tiles. */
+int tvs_batch_get_bucket(const tvs_batch *batch, int32_t i, tvs_batch_bucket *out);
 
 /* Releases the batch's graph and device memory (waits for its work). NULL is ignored. */
 int tvs_batch_destroy(tvs_batch *batch);

@@ -17,6 +17,7 @@ __all__ = [
     "TvsError", "lib", "total_viewshed", "singular_viewshed", "debug_sector_rays", "sector_shape",
     "los_evals", "abi_version", "FLAG_SLOPE_F64", "FLAG_SWEEP_SCAN", "FLAG_ACC_KAHAN32", "FLAG_SLOPE_EXACT", "FLAG_NO_PRUNE",
     "FLAG_COUNT_EVALS", "FLAG_SLOPE_F32", "FLAG_AUTOTUNE", "FLAG_COMPACT", "FLAG_RELOCATE", "Stats", "Batch", "BatchInfo",
+    "BatchBucket",
     "total_viewshed_tiles", "Server", "multiple_viewshed", "singular_mask", "total_viewshed_noalloc",
 ]
 
@@ -65,7 +66,16 @@ class BatchInfo(C.Structure):
     _fields_ = [("tiles", C.c_int32), ("chunks", C.c_int32), ("kernel_launches", C.c_int32),
                 ("waves_per_group", C.c_int32), ("groups", C.c_int32), ("tuned", C.c_int32),
                 ("los_evals", C.c_int64), ("pov_sector_pairs", C.c_int64), ("sweep_evals_done", C.c_int64),
-                ("scratch_bytes", C.c_int64), ("tune_ms", C.c_double)]
+                ("scratch_bytes", C.c_int64), ("tune_ms", C.c_double), ("buckets", C.c_int32), ("pad", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class BatchBucket(C.Structure):
+    _fields_ = [("side_class", C.c_int32), ("reach_class", C.c_int32), ("tiles", C.c_int32),
+                ("longest_side", C.c_int32), ("longest_reach", C.c_int32), ("waves_per_group", C.c_int32),
+                ("groups_per_cu", C.c_int32), ("tuned", C.c_int32), ("items", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -117,6 +127,7 @@ def lib():
         L.tvs_batch_create.argtypes = [C.POINTER(Tile), i32, i32, u32, C.POINTER(C.c_void_p)]
         L.tvs_batch_run.argtypes = [vp, vp]
         L.tvs_batch_get_info.argtypes = [vp, C.POINTER(BatchInfo)]
+        L.tvs_batch_get_bucket.argtypes = [vp, i32, C.POINTER(BatchBucket)]
         L.tvs_batch_destroy.argtypes = [vp]
         L.tvs_total_viewshed_tiles.argtypes = [C.POINTER(Tile), i32, i32, u32, vp]
         u64p = C.POINTER(C.c_uint64)
@@ -135,7 +146,8 @@ def lib():
         for name in ("tvs_total_viewshed", "tvs_singular_viewshed", "tvs_total_viewshed_async",
                      "tvs_singular_viewshed_async", "tvs_total_viewshed_ex", "tvs_singular_viewshed_ex",
                      "tvs_sector_shape", "tvs_debug_sector_rays", "tvs_debug_sector_rays_async", "tvs_los_evals",
-                     "tvs_batch_create", "tvs_batch_run", "tvs_batch_get_info", "tvs_batch_destroy",
+                     "tvs_batch_create", "tvs_batch_run", "tvs_batch_get_info", "tvs_batch_get_bucket",
+                     "tvs_batch_destroy",
                      "tvs_total_viewshed_tiles", "tvs_server_create", "tvs_server_add_grid",
                      "tvs_server_submit_total", "tvs_server_submit_singular", "tvs_server_wait",
                      "tvs_server_copy_map", "tvs_server_release", "tvs_server_get_stats", "tvs_server_destroy",
@@ -379,6 +391,15 @@ class Batch:
         inf = BatchInfo()
         _check(lib().tvs_batch_get_info(self._h, C.byref(inf)))
         return inf
+
+    def buckets(self):
+        """The batch's buckets of tiles (one sweep launch and launch shape each), largest tiles first."""
+        out = []
+        for i in range(self.info().buckets):
+            bk = BatchBucket()
+            _check(lib().tvs_batch_get_bucket(self._h, i, C.byref(bk)))
+            out.append(bk.as_dict())
+        return out
 
     def close(self):
         if getattr(self, "_h", None):

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 SO = os.path.join(HERE, "libtvs.so")
-SOURCES = ["tvs_kernels.hip", "tvs_api.hip", "tvs_batch.hip", "tvs_server.hip"]
+SOURCES = ["tvs_kernels.hip", "tvs_api.hip", "tvs_batch.hip", "tvs_server.hip", "tvs_tune.hip"]
 ARCH = os.environ.get("TVS_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
@@ -37,11 +37,25 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def source_hash() -> str:
+    """Hash of the library sources and header: tuned launch shapes are remembered per build."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "libtvs.h"), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     objs = []
+    tag = f'-DTVS_SOURCE_HASH="{source_hash()}"'
     for src in SOURCES:
         obj = os.path.join(CSRC, src.replace(".hip", ".o"))
-        cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [hipcc(), *HIPCC_FLAGS, tag, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

@@ -126,7 +126,9 @@ int check_host_dem(const float *dem, int rows, int cols) {
 int check_flags(uint32_t flags, bool accumulation) {
     const uint32_t known = TVS_FLAG_SLOPE_F64 | TVS_FLAG_SWEEP_SCAN | TVS_FLAG_SLOPE_EXACT | TVS_FLAG_NO_PRUNE |
                            TVS_FLAG_SLOPE_F32 | TVS_FLAG_RELOCATE |
-                           (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS | TVS_FLAG_COMPACT : 0u);
+                           (accumulation ? TVS_FLAG_ACC_KAHAN32 | TVS_FLAG_COUNT_EVALS | TVS_FLAG_COMPACT |
+                                               TVS_FLAG_AUTOTUNE
+                                         : 0u);
     if (flags & ~known) return fail(TVS_EINVAL, "unsupported flags 0x%x", flags);
     if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
         return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
@@ -276,6 +278,78 @@ struct Timer {
     }
 };
 
+// Waves per workgroup of the lane-per-POV sweep for this call: with TVS_FLAG_AUTOTUNE, timed on up
+// to four sectors spread over the axes (4, 8 and 16 waves; the skewed viewshed buffer is written and
+// later overwritten) and remembered; otherwise a remembered choice for the same size class, or 0
+// (the launcher's choice from the LDS a row takes). Negative: a failure status.
+int sweep_shape(const std::vector<Sector> &S, const std::vector<Chunk> &chunks, int H, int W, int pitch, double h0,
+                uint32_t flags, const float *dem, const float *demT, char *scratch, size_t scratch_bytes,
+                const float2 *tab32, const double2 *tab64, hipStream_t st, bool fused, bool f64, bool scan, bool rcp,
+                bool prune, bool noalloc) {
+    if (scan || noalloc || S.empty()) return 0;
+    int maxWx = 0, maxK = 0;
+    for (const Sector &s : S) {
+        maxWx = std::max(maxWx, s.Wx);
+        maxK = std::max(maxK, std::min(s.K, s.Wx));
+    }
+    if (!sweep_row_fits(maxWx, f64)) return 0;
+    const TuneKey key{1, (int)f64, (int)rcp, ceil_log2(maxWx), ceil_log2(maxK + 1)};
+    int a = 0, b = 0;
+    if (!(flags & TVS_FLAG_AUTOTUNE)) return tune_lookup(key, a, b) ? a : 0;
+    // a sample of sectors spread over the axes that fits the skewed buffers
+    const size_t elem = fused ? 0 : (f64 ? sizeof(double) : sizeof(float));
+    std::vector<Sector> smp;
+    size_t bytes = 0;
+    const int n = (int)S.size();
+    for (int i = 0; i < 4; ++i) {
+        const Sector &s = S[(size_t)i * n / 4];
+        const size_t add = (size_t)s.prows * pitch * (elem + sizeof(uint32_t));
+        if (!smp.empty() && (bytes + add > scratch_bytes || smp.size() >= (size_t)TVS_CHUNK)) break;
+        if (i > 0 && (size_t)i * n / 4 == (size_t)(i - 1) * n / 4) continue;
+        smp.push_back(s);
+        bytes += add;
+    }
+    Chunk c{0, (int)smp.size(), bytes, 0, 0};
+    for (const Sector &s : smp) {
+        c.maxRows = std::max(c.maxRows, s.nrows);
+        c.maxWx = std::max(c.maxWx, s.Wx);
+    }
+    ChunkArgs ca = chunk_args(smp, c, H, W, pitch, h0);
+    const int64_t elems = (int64_t)(bytes / (elem + sizeof(uint32_t)));
+    void *skw = fused ? nullptr : scratch;
+    uint32_t *V = (uint32_t *)(scratch + (size_t)elems * elem);
+    if (!fused) HIPCHK(launch_relocate(ca, c.maxWx, c.maxRows, dem, skw, f64, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(TVS_EDEVICE, "event creation failed");
+    }
+    float best = 1e30f;
+    int pick = 0;
+    int rc = TVS_OK;
+    for (int cand : {4, 8, 16}) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && rc == TVS_OK; ++rep)  // the first run warms the caches
+            if (hipEventRecord(e0, st) != hipSuccess ||
+                launch_sweep(ca, c.maxWx, c.maxRows, dem, demT, skw, V, tab32, tab64, f64, false, rcp, prune, nullptr,
+                             st, cand) != hipSuccess ||
+                hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                rc = fail(TVS_EDEVICE, "sweep shape timing failed: %s", hipGetErrorString(hipGetLastError()));
+        if (rc != TVS_OK) break;
+        if (ms < best) {
+            best = ms;
+            pick = cand;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != TVS_OK) return rc;
+    tune_store(key, pick, 0);
+    return pick;
+}
+
 // The total viewshed on the device: one chunk of sectors at a time, sweep (each workgroup gathering
 // its skewed row from the grid; with TVS_FLAG_RELOCATE a relocation launch writes skwDEM first) ->
 // back-projection, the per-cell sum carried in d_out (double) or in float Kahan scratch.
@@ -368,6 +442,9 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         HIPCHK(launch_transpose(d_dem, demT, H, W, st));
         HIPCHK(tm.mark());
     }
+    const int nw = sweep_shape(S, chunks, H, W, pitch, h0, flags, d_dem, demT, skwV, maxChunk, tab32, tab64, st,
+                               fused, f64, scan, rcp, prune, fixed != nullptr);
+    if (nw < 0) return nw;
     int64_t evals = 0, pairs = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const Chunk &c = chunks[ci];
@@ -383,7 +460,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         }
         HIPCHK(tm.begin(1));
         HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, d_dem, demT, skw, V, tab32, tab64, f64, scan, rcp, prune, work,
-                            st));
+                            st, nw));
         HIPCHK(tm.mark());
         if (d_debugV) {
             const Sector &s = S[0];

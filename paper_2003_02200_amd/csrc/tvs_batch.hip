@@ -5,9 +5,11 @@
 // (tile, sector, skewed row) item of every tile -- gathering each skewed row straight from its
 // tile's DEM (the relocation fused into the sweep) -- and one back-projection launch covers all
 // tiles. The whole pass is captured once into a HIP graph and replayed; the work lists live in
-// device memory and a replay only resets the item counters (with a fill kernel). The launch
-// shape of the persistent sweep (waves per workgroup, workgroups per CU) is picked by timing
-// candidates on a sample of the batch, and remembered per size class.
+// device memory and a replay only resets the item counters (with a fill kernel). Tiles are grouped
+// into buckets by the size classes of their longest side and their longest line of sight; each
+// bucket has its own sweep launch per chunk, sized for its rows, and its own launch shape (waves
+// per workgroup; persistent workgroups per CU, or one workgroup per item), picked by timing
+// candidates on a sample of the bucket's items and remembered per device and library build.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -16,9 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <map>
-#include <mutex>
 #include <new>
-#include <tuple>
 #include <vector>
 
 #include "../../include/libtvs.h"
@@ -39,26 +39,27 @@ struct ChunkPlan {
     int nitems;       // (tile, sector, skewed row) items
     int nblocks;      // back-projection blocks over every tile
     size_t vbytes;    // skewed viewshed rows of every tile and sector of the chunk
+    std::vector<int> bucket_items;  // per bucket: its items (they follow each other in bucket order)
 };
 
 struct Shape {
-    int waves;   // wavefronts per workgroup of the persistent sweep
-    int per_cu;  // workgroups per CU
+    int waves;   // wavefronts per workgroup of the sweep
+    int per_cu;  // persistent workgroups per CU; 0: one workgroup per item
 };
 
 constexpr Shape kDefaultShape{4, 8};
-const Shape kCandidates[] = {{2, 4}, {2, 8}, {2, 16}, {4, 2}, {4, 4}, {4, 8}, {8, 1}, {8, 2}, {8, 4}};
+const Shape kCandidates[] = {{2, 4}, {2, 8}, {2, 16}, {4, 2}, {4, 4}, {4, 8}, {8, 1},
+                             {8, 2}, {8, 4}, {2, 0}, {4, 0}, {8, 0}};
 
-// Shapes chosen by timing, per (precision, slope form, size class of the longest row, of the
-// distance bound).
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, Shape> g_tuned;
-
-int ceil_log2(int64_t v) {
-    int r = 0;
-    while (((int64_t)1 << r) < v) ++r;
-    return r;
-}
+// Tiles whose longest side and longest line of sight (capped at the side) fall in the same ceil(log2)
+// classes: one sweep launch per chunk, sized for their rows, with one launch shape.
+struct Bucket {
+    int side_b, rho_b;  // size classes
+    int maxWx, maxK;    // longest side and line of sight of its tiles
+    int ntiles;
+    Shape shape;
+    bool tuned;
+};
 
 int cu_count(int dev) {
     int v = 0;
@@ -87,6 +88,8 @@ struct tvs_batch {
     bool transpose = false;                    // the pass transposes the tiles into demT first
     bool persistent = true;                    // persistent sweep (else one workgroup per item)
     std::vector<ChunkPlan> chunks;
+    std::vector<Bucket> buckets;
+    std::vector<int> tile_bucket;  // per tile
     int maxWx = 0, tabN = 0, maxK = 0;
     bool counted = false;
     int64_t evals = 0, pairs = 0;
@@ -100,8 +103,7 @@ struct tvs_batch {
     BatchTile *btiles = nullptr;
     uint32_t *items = nullptr;
     uint32_t *V = nullptr;
-    Shape shape = kDefaultShape;
-    int grid = 0;
+    int cus = 256;
     bool tuned = false;
     double tune_ms = 0.0;
     int launches = 0;
@@ -148,6 +150,40 @@ int check_batch_flags(uint32_t flags) {
     if ((flags & TVS_FLAG_SLOPE_F32) && (flags & TVS_FLAG_SLOPE_F64))
         return fail(TVS_EINVAL, "TVS_FLAG_SLOPE_F32 and TVS_FLAG_SLOPE_F64 exclude each other");
     return TVS_OK;
+}
+
+// Buckets of the batch's tiles (largest side first), each with its cached shape or the default.
+void plan_buckets(tvs_batch *b) {
+    std::map<std::pair<int, int>, int> idx;
+    std::vector<std::pair<int, int>> keys(b->ntiles);
+    for (int t = 0; t < b->ntiles; ++t) {
+        const tvs_tile &T = b->tiles[t];
+        const int side = std::max(T.rows, T.cols);
+        int k = 0;
+        for (const Sector &s : b->sectors[t]) k = std::max(k, std::min(s.K, std::max(s.Hx, s.Wx)));
+        keys[t] = std::make_pair(-ceil_log2(side), ceil_log2(k + 1));
+        idx[keys[t]] = 0;
+    }
+    for (auto &kv : idx) {
+        kv.second = (int)b->buckets.size();
+        Bucket bk{-kv.first.first, kv.first.second, 0, 0, 0, kDefaultShape, false};
+        int a = 0, c = 0;
+        if (tune_lookup(TuneKey{0, (int)b->f64, (int)b->rcp, bk.side_b, bk.rho_b}, a, c)) {
+            bk.shape = Shape{a, c};
+            bk.tuned = true;
+        }
+        b->buckets.push_back(bk);
+    }
+    b->tile_bucket.resize(b->ntiles);
+    for (int t = 0; t < b->ntiles; ++t) {
+        const int x = idx[keys[t]];
+        b->tile_bucket[t] = x;
+        Bucket &bk = b->buckets[x];
+        const tvs_tile &T = b->tiles[t];
+        bk.maxWx = std::max(bk.maxWx, std::max(T.rows, T.cols));
+        for (const Sector &s : b->sectors[t]) bk.maxK = std::max(bk.maxK, std::min(s.K, std::max(s.Hx, s.Wx)));
+        bk.ntiles += 1;
+    }
 }
 
 // Sector groups of the batch: every tile's sectors [k0, k1) together, within the scratch budget
@@ -228,20 +264,28 @@ void build_tables(tvs_batch *b, std::vector<BatchEnt> &ent, std::vector<BatchTil
             bt.push_back(q);
         }
         c.nblocks = blk;
-        for (int t : order)
-            for (int x = 0; x < nsec; ++x) {
-                const int nr = b->sectors[t][c.k0 + x].nrows;
-                const uint32_t e = (uint32_t)(t * nsec + x);
-                for (int i = 0; i < nr; ++i) items.push_back((e << 16) | (uint32_t)middle_out(i, nr));
+        c.bucket_items.assign(b->buckets.size(), 0);
+        for (size_t bk = 0; bk < b->buckets.size(); ++bk) {
+            const size_t before = items.size();
+            for (int t : order) {
+                if (b->tile_bucket[t] != (int)bk) continue;
+                for (int x = 0; x < nsec; ++x) {
+                    const int nr = b->sectors[t][c.k0 + x].nrows;
+                    const uint32_t e = (uint32_t)(t * nsec + x);
+                    for (int i = 0; i < nr; ++i) items.push_back((e << 16) | (uint32_t)middle_out(i, nr));
+                }
             }
+            c.bucket_items[bk] = (int)(items.size() - before);
+        }
         c.nitems = (int)(items.size() - c.item_off);
     }
 }
 
 hipError_t enqueue_pass(tvs_batch *b, hipStream_t st) {
     hipError_t e;
+    const size_t nb = b->buckets.size();
     if ((e = launch_divtab(b->tab32, b->tab64, b->tabN, st)) != hipSuccess) return e;
-    if ((e = launch_fill_u32(b->counters, (int64_t)b->chunks.size(), 0u, st)) != hipSuccess) return e;
+    if ((e = launch_fill_u32(b->counters, (int64_t)(b->chunks.size() * nb), 0u, st)) != hipSuccess) return e;
     b->launches = 2;
     if (b->transpose)
         for (int t = 0; t < b->ntiles; ++t) {
@@ -256,54 +300,69 @@ hipError_t enqueue_pass(tvs_batch *b, hipStream_t st) {
     }
     for (size_t ci = 0; ci < b->chunks.size(); ++ci) {
         const ChunkPlan &c = b->chunks[ci];
-        if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + c.item_off, c.nitems,
-                                    b->persistent ? b->counters + ci : nullptr, b->V,
-                                    b->tab32, b->tab64, b->f64, b->rcp, b->shape.waves, b->grid, b->maxWx,
-                                    b->maxK, b->count ? b->work : nullptr, st)) != hipSuccess)
-            return e;
+        size_t off = c.item_off;
+        for (size_t bk = 0; bk < nb; ++bk) {
+            const int cnt = c.bucket_items[bk];
+            if (cnt == 0) continue;
+            const Bucket &B = b->buckets[bk];
+            const bool pers = b->persistent && B.shape.per_cu > 0;
+            if ((e = launch_sweep_batch(b->ent + c.ent_off, b->items + off, cnt,
+                                        pers ? b->counters + ci * nb + bk : nullptr, b->V, b->tab32, b->tab64,
+                                        b->f64, b->rcp, B.shape.waves, pers ? b->cus * B.shape.per_cu : 1, B.maxWx,
+                                        B.maxK, b->count ? b->work : nullptr, st)) != hipSuccess)
+                return e;
+            off += (size_t)cnt;
+            ++b->launches;
+        }
         if ((e = launch_backproj_batch(b->btiles + c.tile_off, b->ntiles, c.nblocks, b->ent + c.ent_off,
                                        c.k1 - c.k0, b->V, ci == 0, st)) != hipSuccess)
             return e;
-        b->launches += 2;
+        ++b->launches;
     }
     return hipSuccess;
 }
 
-// Times every candidate shape on a strided sample of the first chunk's items (an eager pass
-// first builds the reciprocal tables) and keeps the fastest.
-int autotune(tvs_batch *b, int cus) {
+// Times every candidate shape on a strided sample of each bucket's items in the first chunk (an
+// eager pass first builds the reciprocal tables), keeps the fastest per bucket and remembers it.
+int autotune(tvs_batch *b) {
     const ChunkPlan &c = b->chunks[0];
-    const int stride = std::max(1, c.nitems / 16384);
-    std::vector<uint32_t> sample;
     std::vector<uint32_t> all((size_t)c.nitems);
     HIPCHK(hipMemcpy(all.data(), b->items + c.item_off, all.size() * 4, hipMemcpyDeviceToHost));
-    for (int i = 0; i < c.nitems; i += stride) sample.push_back(all[i]);
     uint32_t *d_sample = nullptr;
-    unsigned int *d_ctr = nullptr;
-    HIPCHK(hipMalloc((void **)&d_sample, sample.size() * 4 + 256));
-    d_ctr = (unsigned int *)((char *)d_sample + align256(sample.size() * 4));
+    HIPCHK(hipMalloc((void **)&d_sample, (size_t)16384 * 4 + 256));
+    unsigned int *d_ctr = (unsigned int *)((char *)d_sample + (size_t)16384 * 4);
     const auto t0 = std::chrono::steady_clock::now();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = TVS_OK;
-    float best = 1e30f;
-    Shape pick = kDefaultShape;
-    do {
-        if (hipMemcpy(d_sample, sample.data(), sample.size() * 4, hipMemcpyHostToDevice) != hipSuccess ||
-            hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
-            launch_divtab(b->tab32, b->tab64, b->tabN, b->cap) != hipSuccess) {
-            rc = fail(TVS_EDEVICE, "autotune set-up failed: %s", hipGetErrorString(hipGetLastError()));
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess ||
+        launch_divtab(b->tab32, b->tab64, b->tabN, b->cap) != hipSuccess)
+        rc = fail(TVS_EDEVICE, "autotune set-up failed: %s", hipGetErrorString(hipGetLastError()));
+    size_t off = 0;
+    for (size_t bk = 0; bk < b->buckets.size() && rc == TVS_OK; ++bk) {
+        Bucket &B = b->buckets[bk];
+        const int cnt = c.bucket_items[bk];
+        const size_t first = off;
+        off += (size_t)cnt;
+        if (cnt == 0) continue;
+        const int stride = std::max(1, (cnt + 16383) / 16384);
+        std::vector<uint32_t> sample;
+        for (int i = 0; i < cnt; i += stride) sample.push_back(all[first + i]);
+        if (hipMemcpy(d_sample, sample.data(), sample.size() * 4, hipMemcpyHostToDevice) != hipSuccess) {
+            rc = fail(TVS_EDEVICE, "autotune upload failed");
             break;
         }
-        for (const Shape &s : kCandidates) {
-            const int grid = cus * s.per_cu;
+        float best = 1e30f;
+        Shape pick = B.shape;
+        for (const Shape &sh : kCandidates) {
             float ms = 0.f;
             for (int rep = 0; rep < 2 && rc == TVS_OK; ++rep) {  // the first run warms the caches
+                const bool pers = sh.per_cu > 0;
                 if (launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
-                                       s.waves, 0, b->maxWx, b->maxK, nullptr, b->cap) != hipSuccess ||
+                                       sh.waves, 0, B.maxWx, B.maxK, nullptr, b->cap) != hipSuccess ||
                     launch_fill_u32(d_ctr, 1, 0u, b->cap) != hipSuccess || hipEventRecord(e0, b->cap) != hipSuccess ||
-                    launch_sweep_batch(b->ent + c.ent_off, d_sample, (int)sample.size(), d_ctr, b->V, b->tab32,
-                                       b->tab64, b->f64, b->rcp, s.waves, grid, b->maxWx, b->maxK,
-                                       nullptr, b->cap) != hipSuccess ||
+                    launch_sweep_batch(b->ent + c.ent_off, d_sample, (int)sample.size(), pers ? d_ctr : nullptr, b->V,
+                                       b->tab32, b->tab64, b->f64, b->rcp, sh.waves, pers ? b->cus * sh.per_cu : 1,
+                                       B.maxWx, B.maxK, nullptr, b->cap) != hipSuccess ||
                     hipEventRecord(e1, b->cap) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                     hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                     rc = fail(TVS_EDEVICE, "autotune run failed: %s", hipGetErrorString(hipGetLastError()));
@@ -311,16 +370,19 @@ int autotune(tvs_batch *b, int cus) {
             if (rc != TVS_OK) break;
             if (ms < best) {
                 best = ms;
-                pick = s;
+                pick = sh;
             }
         }
-    } while (0);
+        if (rc != TVS_OK) break;
+        B.shape = pick;
+        B.tuned = true;
+        tune_store(TuneKey{0, (int)b->f64, (int)b->rcp, B.side_b, B.rho_b}, pick.waves, pick.per_cu);
+    }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(b->cap);
     (void)hipFree(d_sample);
     if (rc != TVS_OK) return rc;
-    b->shape = pick;
     b->tuned = true;
     b->tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return TVS_OK;
@@ -351,6 +413,8 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     if (sweep_lds_bytes(b->maxWx, b->f64) + 64 > (size_t)lds_limit(b->dev))
         return fail(TVS_ERANGE, "a skewed row of %d %s samples does not fit the workgroup LDS", b->maxWx,
                     b->f64 ? "double" : "float");
+    b->cus = cu_count(b->dev);
+    plan_buckets(b);
     if (int rc = plan_chunks(b, scratch_budget())) return rc;
     std::vector<BatchEnt> ent;
     std::vector<BatchTile> bt;
@@ -361,7 +425,7 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     const size_t nch = b->chunks.size();
     const size_t sz_tab32 = align256((size_t)b->tabN * sizeof(float2));
     const size_t sz_tab64 = align256((size_t)b->tabN * sizeof(double2));
-    const size_t sz_ctr = align256(nch * sizeof(unsigned int));
+    const size_t sz_ctr = align256(nch * b->buckets.size() * sizeof(unsigned int));
     const size_t sz_work = align256(64 * sizeof(unsigned long long));
     const size_t sz_ent = align256(ent.size() * sizeof(BatchEnt));
     const size_t sz_bt = align256(bt.size() * sizeof(BatchTile));
@@ -400,24 +464,15 @@ int create(const tvs_tile *tiles, int ntiles, int n, uint32_t flags, tvs_batch *
     HIPCHK(hipMemset(b->work, 0, 64 * sizeof(unsigned long long)));
     HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
 
-    const int cus = cu_count(b->dev);
-    const auto key = std::make_tuple((int)b->f64, (int)b->rcp, ceil_log2(b->maxWx), ceil_log2(b->maxK + 1));
     if (flags & TVS_FLAG_AUTOTUNE) {
-        if (int rc = autotune(b, cus)) return rc;
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        g_tuned[key] = b->shape;
+        if (int rc = autotune(b)) return rc;
     } else {
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) {
-            b->shape = it->second;
-            b->tuned = true;
-        }
+        for (const Bucket &B : b->buckets) b->tuned |= B.tuned;  // shapes remembered from earlier timing
     }
-    b->grid = cus * b->shape.per_cu;
-    // raise the sweep's LDS limit before capture (no attribute calls inside a graph)
-    HIPCHK(launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
-                              b->shape.waves, 0, b->maxWx, b->maxK, nullptr, b->cap));
+    // raise the sweeps' LDS limits before capture (no attribute calls inside a graph)
+    for (const Bucket &B : b->buckets)
+        HIPCHK(launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b->f64, b->rcp,
+                                  B.shape.waves, 0, B.maxWx, B.maxK, nullptr, b->cap));
     HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     const hipError_t le = enqueue_pass(b, b->cap);
     const hipError_t ce = hipStreamEndCapture(b->cap, &b->graph);
@@ -466,6 +521,8 @@ int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, i
     b.tabN = b.maxWx;
     if (!batch_rows_fit(b.maxWx, b.f64))
         return fail(TVS_ERANGE, "a skewed row of %d samples does not fit the workgroup LDS", b.maxWx);
+    b.cus = cu_count(b.dev);
+    plan_buckets(&b);
     if (int rc = plan_chunks(&b, budget)) return rc;
     std::vector<BatchEnt> ent;
     std::vector<BatchTile> bt;
@@ -477,7 +534,7 @@ int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, i
     const size_t sz_ent = align256(ent.size() * sizeof(BatchEnt)), sz_bt = align256(bt.size() * sizeof(BatchTile)),
                  sz_items = align256(items.size() * sizeof(uint32_t));
     const size_t sz_tab32 = align256((size_t)b.tabN * sizeof(float2)), sz_tab64 = align256((size_t)b.tabN * sizeof(double2)),
-                 sz_ctr = align256(nch * sizeof(unsigned int));
+                 sz_ctr = align256(nch * b.buckets.size() * sizeof(unsigned int));
     const size_t host_bytes = sz_ent + sz_bt + sz_items;
     if (stage.cap < host_bytes) {
         const size_t want = std::max(host_bytes, (size_t)2 * stage.cap);
@@ -505,18 +562,11 @@ int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, i
     b.counters = (unsigned int *)(d + host_bytes + sz_tab32 + sz_tab64);
     b.V = (uint32_t *)(d + host_bytes + sz_tab32 + sz_tab64 + sz_ctr);
     b.work = nullptr;
-    const int cus = cu_count(b.dev);
-    {
-        const auto key = std::make_tuple((int)b.f64, (int)b.rcp, ceil_log2(b.maxWx), ceil_log2(b.maxK + 1));
-        std::lock_guard<std::mutex> g(g_tune_mu);
-        auto it = g_tuned.find(key);
-        if (it != g_tuned.end()) b.shape = it->second;
-    }
-    b.grid = cus * b.shape.per_cu;
     hipError_t e = hipMemcpyAsync(d, h, host_bytes, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-        e = launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b.f64, b.rcp, b.shape.waves, 0,
-                               b.maxWx, b.maxK, nullptr, st);
+    for (const Bucket &B : b.buckets)
+        if (e == hipSuccess)
+            e = launch_sweep_batch(nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr, b.f64, b.rcp, B.shape.waves,
+                                   0, B.maxWx, B.maxK, nullptr, st);
     if (e == hipSuccess) e = enqueue_pass(&b, st);
     const hipError_t fe = hipFreeAsync(d, st);
     if (e != hipSuccess) return fail(TVS_EDEVICE, "batch launch: %s", hipGetErrorString(e));
@@ -590,8 +640,9 @@ int tvs_batch_get_info(const tvs_batch *batch, tvs_batch_info *info) {
     info->tiles = b->ntiles;
     info->chunks = (int32_t)b->chunks.size();
     info->kernel_launches = b->launches;
-    info->waves_per_group = b->shape.waves;
-    info->groups = b->grid;
+    info->waves_per_group = b->buckets[0].shape.waves;  // the bucket of the largest tiles
+    info->groups = b->buckets[0].shape.per_cu ? b->cus * b->buckets[0].shape.per_cu : 0;
+    info->buckets = (int32_t)b->buckets.size();
     info->tuned = b->tuned ? 1 : 0;
     info->los_evals = b->evals;
     info->pov_sector_pairs = b->pairs;
@@ -603,6 +654,25 @@ int tvs_batch_get_info(const tvs_batch *batch, tvs_batch_info *info) {
         HIPCHK(hipMemcpy(h, b->work, sizeof(h), hipMemcpyDeviceToHost));
         for (int x = 0; x < 64; ++x) info->sweep_evals_done += (int64_t)h[x];
     }
+    return TVS_OK;
+}
+
+int tvs_batch_get_bucket(const tvs_batch *batch, int32_t i, tvs_batch_bucket *out) {
+    g_err[0] = 0;
+    if (!batch || !out) return fail(TVS_EINVAL, "null batch or out");
+    if (i < 0 || i >= (int)batch->buckets.size())
+        return fail(TVS_EINVAL, "bucket %d outside [0, %d)", i, (int)batch->buckets.size());
+    const Bucket &B = batch->buckets[i];
+    memset(out, 0, sizeof(*out));
+    out->side_class = B.side_b;
+    out->reach_class = B.rho_b;
+    out->tiles = B.ntiles;
+    out->longest_side = B.maxWx;
+    out->longest_reach = B.maxK;
+    out->waves_per_group = B.shape.waves;
+    out->groups_per_cu = B.shape.per_cu;
+    out->tuned = B.tuned ? 1 : 0;
+    for (const ChunkPlan &c : batch->chunks) out->items += c.bucket_items[i];
     return TVS_OK;
 }
 

@@ -68,6 +68,19 @@ int total_on_stream(const float *d_dem, int H, int W, double dx, double h0, int 
 // Device scratch that total_on_stream takes for these arguments.
 size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t flags, size_t budget);
 
+// Launch shapes chosen by timing (tvs_tune.hip): kind 0 the batched sweep (a = waves per
+// workgroup, b = workgroups per CU, 0 for one workgroup per item), kind 1 the single-grid sweep
+// (a = waves per workgroup); keyed by decision precision and slope form and the ceil(log2) size
+// classes of the longest skewed row and of the longest line of sight (+1). Kept per device and
+// library build, in memory and in a cache file.
+struct TuneKey {
+    int kind, f64, rcp, side_b, rho_b;
+};
+bool tune_lookup(const TuneKey &k, int &a, int &b);
+void tune_store(const TuneKey &k, int a, int b);
+const char *source_hash();
+int ceil_log2(int64_t v);
+
 // Pinned host staging owned by a caller of batch_enqueue (grown there, freed by the owner).
 struct PinnedStaging {
     void *p = nullptr;

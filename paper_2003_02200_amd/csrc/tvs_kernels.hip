@@ -1591,7 +1591,7 @@ static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int m
 
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
-                        bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
+                        bool rcp, bool prune, unsigned long long *work, hipStream_t st, int nw) {
     RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
     if (!sweep_row_fits(maxWx, f64)) {
         int maxK = 0;
@@ -1604,7 +1604,7 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float 
     for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
     // without the early exit or in the lane-per-target variant no sliding maxima
     const size_t lds = sweep_lds_launch(maxWx, f64, prune && !scan ? maxK : INT_MAX, b.rmq, slide);
-    switch (sweep_waves(lds)) {
+    switch (nw == 4 || nw == 8 || nw == 16 ? nw : sweep_waves(lds)) {
     case 4: return sweep_nw<4>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
     case 8: return sweep_nw<8>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);
     default: return sweep_nw<16>(b, src, grid, lds, skw, V, tab32, tab64, f64, scan, rcp, prune, slide, work, st);

@@ -61,7 +61,7 @@ def test_rejects_bad_flag_combinations(tvs):
     d = np.zeros(4, np.float32)
     out = np.zeros(4, np.float64)
     vp = C.c_void_p
-    for flags in (0x80, 0x400, 0x80000000, 0x41):  # 0x41: float and double decisions together
+    for flags in (0x800, 0x400, 0x80000000, 0x41):  # 0x41: float and double decisions together
         rc = L.tvs_total_viewshed_ex(d.ctypes.data_as(vp), 2, 2, 10.0, 1.5, 4, math.inf, out.ctypes.data_as(vp),
                                      flags, None, None)
         assert rc == -1, flags

@@ -81,8 +81,15 @@ def test_batch_equals_per_tile_and_oracle(tvs, orc, flags, prec):
             o.fill_(3.0)
         torch.cuda.synchronize()
     inf = b.info()
-    # tables and counters, the tiles transposed (n >= 2), one sweep and one back-projection per chunk
-    assert inf.tiles == len(TILES) and inf.chunks >= 1 and inf.kernel_launches == 2 + len(TILES) + 2 * inf.chunks
+    # tables and counters, the tiles transposed (n >= 2), per chunk one sweep per bucket of tiles and
+    # one back-projection
+    assert inf.tiles == len(TILES) and inf.chunks >= 1 and inf.buckets >= 1
+    assert inf.kernel_launches == 2 + len(TILES) + inf.chunks * (inf.buckets + 1)
+    bks = b.buckets()
+    assert sum(bk["tiles"] for bk in bks) == len(TILES)
+    nrows = sum(tvs.sector_shape(H, W, n, k)[0] for (H, W, *_r) in TILES for k in range(n))
+    assert sum(bk["items"] for bk in bks) == nrows
+    assert [bk["side_class"] for bk in bks] == sorted((bk["side_class"] for bk in bks), reverse=True)
     ev = sum(tvs.los_evals(H, W, dx, n, R)[0] for (H, W, dx, h0, R) in TILES)
     assert inf.los_evals == ev
     b.close()
@@ -162,9 +169,14 @@ def test_batch_autotune(tvs):
         ref = tvs.total_viewshed(dems[x], dx, h0, n, R)
         torch.cuda.synchronize()
         np.testing.assert_allclose(outs[x].cpu().numpy(), ref.cpu().numpy(), rtol=1e-13, atol=0)
-    # the shape is remembered for the size class
+    bks = b.buckets()
+    assert all(bk["tuned"] == 1 and bk["waves_per_group"] in (2, 4, 8) and bk["groups_per_cu"] in (0, 1, 2, 4, 8, 16)
+               for bk in bks)
+    # the shapes are remembered per size class
     b2 = tvs.Batch(tl, n)
-    assert b2.info().tuned == 1 and b2.info().waves_per_group == inf.waves_per_group
+    assert b2.info().tuned == 1
+    assert [(x["waves_per_group"], x["groups_per_cu"]) for x in b2.buckets()] == \
+        [(x["waves_per_group"], x["groups_per_cu"]) for x in bks]
     b.close()
     b2.close()
 
@@ -196,3 +208,53 @@ def test_batch_long_lines_of_sight(tvs):
         done += st.sweep_evals_done
     assert b.info().sweep_evals_done == done
     b.close()
+
+
+_TUNE_SCRIPT = r"""
+import json, sys
+sys.path.insert(0, sys.argv[1])
+import torch
+import paper_2003_02200_amd as tvs
+from synth import fractal_dem
+torch.cuda.set_device(0)
+tiles = [(300, 280, 10.0, 1.5, 3000.0), (70, 90, 10.0, 5.0, 900.0)]
+dems = [torch.from_numpy(fractal_dem(max(H, W), 60 + x, 0.6, 900.0)[:H, :W].copy()).cuda()
+        for x, (H, W, *_r) in enumerate(tiles)]
+outs = [torch.zeros(d.shape, dtype=torch.float64, device="cuda") for d in dems]
+flags = tvs.FLAG_AUTOTUNE if sys.argv[2] == "tune" else 0
+b = tvs.Batch([(dems[x], outs[x], *tiles[x][2:]) for x in range(2)], 12, flags=flags)
+b.run()
+m = tvs.total_viewshed(dems[0], 10.0, 1.5, 12, 3000.0, flags=flags)
+torch.cuda.synchronize()
+print(json.dumps({"buckets": b.buckets(), "sum": float(outs[0].sum()), "single": float(m.sum())}))
+b.close()
+"""
+
+
+def test_tuned_shapes_persist_across_processes(tvs, tmp_path):
+    """Shapes timed in one process (batch buckets and the single-grid sweep) are written to the tune
+    cache with the device and library build, and a fresh process on the same build starts with them;
+    maps are the same with any shape."""
+    import json
+    import os
+    import subprocess
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, TVS_TUNE_CACHE=str(tmp_path / "tune.txt"))
+    note("tune cache: timing process")
+    a = subprocess.run([sys.executable, "-c", _TUNE_SCRIPT, root, "tune"], env=env, capture_output=True, text=True,
+                       timeout=180)
+    assert a.returncode == 0, a.stderr[-2000:]
+    ra = json.loads(a.stdout.strip().splitlines()[-1])
+    lines = (tmp_path / "tune.txt").read_text().splitlines()
+    assert len(lines) >= len(ra["buckets"]) + 1  # every bucket, and the single-grid sweep (kind 1)
+    assert {ln.split()[2] for ln in lines} == {"0", "1"}
+    note("tune cache: fresh process")
+    b = subprocess.run([sys.executable, "-c", _TUNE_SCRIPT, root, "reuse"], env=env, capture_output=True, text=True,
+                       timeout=180)
+    assert b.returncode == 0, b.stderr[-2000:]
+    rb = json.loads(b.stdout.strip().splitlines()[-1])
+    assert all(x["tuned"] == 1 for x in rb["buckets"])
+    assert [(x["waves_per_group"], x["groups_per_cu"]) for x in rb["buckets"]] == \
+        [(x["waves_per_group"], x["groups_per_cu"]) for x in ra["buckets"]]
+    assert ra["sum"] == rb["sum"] and ra["single"] == rb["single"]
