@@ -142,10 +142,10 @@ def main():
     if args.mode == "multiple":
         return bench_multiple(args)
     line = bench_single(args)
+    if not args.no_serve and args.workload == "tvs2000" and args.flags == 0:
+        line["serve"] = bench_serve(args, 8.0, cold=False)
     if not args.no_batch and args.workload == "tvs2000" and args.flags == 0:
         line["batch"] = bench_batch(args, args.batch_tiles, 2, 1)
-    if not args.no_serve and args.workload == "tvs2000" and args.flags == 0:
-        line["serve"] = bench_serve(args, 5.0, cold=False)
     print(json.dumps(line), flush=True)
 
 

@@ -146,8 +146,10 @@ int tvs_singular_viewshed(const float *dem, int32_t rows, int32_t cols, double s
                           int32_t pov_row, int32_t pov_col, double *out_area, uint8_t *out_mask);
 
 /* Device-resident, stream-ordered total viewshed: d_dem and d_out are device pointers
- * (rows*cols float / double). Elevations are not inspected on the host: the caller
- * guarantees they are finite and 0 or at least 2^-60 m in magnitude. */
+ * (rows*cols float / double). Elevations are not read on the host; they are checked on the device
+ * (finite, and 0 or at least 2^-60 m in magnitude), and a grid that breaks the rule gives a map of
+ * NaN in every cell: the status, returned before the work runs, cannot report it. The same holds for
+ * tvs_total_viewshed_ex, tvs_total_viewshed_noalloc and tvs_total_viewshed_tiles. */
 int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing,
                              double obs_height, int32_t n_sectors, double max_dist,
                              double *d_out, void *hip_stream);

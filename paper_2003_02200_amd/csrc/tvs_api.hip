@@ -357,9 +357,12 @@ int sweep_shape(const std::vector<Sector> &S, const std::vector<Chunk> &chunks, 
 // `fixed_bytes` at `fixed` (the allocation-free entry point's static array), the skewed buffers use
 // the compacted layout, and sector chunks are sized to fit; a sector that alone does not fit is
 // rejected with TVS_ERANGE before anything is enqueued.
+// With check_dem the grid's elevations are checked on the device (entry points that take device grids
+// and never read them on the host): a grid that breaks the rule gives a map of NaN.
 int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, double R, double *d_out,
               uint32_t flags, tvs_stats *stats, hipStream_t st, int debug_sector, uint32_t *d_debugV,
-              int *debug_pitch, size_t budget = 0, void *fixed = nullptr, size_t fixed_bytes = 0) {
+              int *debug_pitch, size_t budget = 0, void *fixed = nullptr, size_t fixed_bytes = 0,
+              bool check_dem = false) {
     const bool f64 = (flags & TVS_FLAG_SLOPE_F32) == 0;
     const bool scan = (flags & TVS_FLAG_SWEEP_SCAN) != 0;
     const bool kahan = (flags & TVS_FLAG_ACC_KAHAN32) != 0;
@@ -393,8 +396,8 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     const size_t tabBytes = (size_t)tabN * (sizeof(float2) + sizeof(double2));
     const size_t kahanBytes = kahan ? (size_t)H * W * 2 * sizeof(float) : 0;
     constexpr int kWorkSlots = 64;  // evaluation counters of the sweep (TVS_FLAG_COUNT_EVALS)
-    // every carved piece is rounded up to 256 bytes: at most 6 pieces besides the skewed buffers
-    const size_t fixedParts = tabBytes + kahanBytes + demTBytes + 256 * 4 + kWorkSlots * 8 + 7 * 256;
+    // every carved piece is rounded up to 256 bytes: at most 7 pieces besides the skewed buffers
+    const size_t fixedParts = tabBytes + kahanBytes + demTBytes + 256 * 4 + kWorkSlots * 8 + 256 + 8 * 256;
     if (fixed && fixed_bytes <= fixedParts)
         return fail(TVS_ERANGE, "tables of a %d x %d grid (%zu bytes) exceed the %zu-byte allocation-free scratch",
                     H, W, fixedParts, fixed_bytes);
@@ -430,6 +433,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     float *kc = kahan ? (float *)carve((size_t)H * W * sizeof(float)) : nullptr;
     unsigned long long *work = count ? (unsigned long long *)carve(kWorkSlots * 8) : nullptr;
     float *demT = needT ? (float *)carve(demTBytes) : nullptr;
+    uint32_t *bad = (uint32_t *)carve(256);
     char *skwV = (char *)carve(maxChunk);
 
     Timer tm;
@@ -437,6 +441,11 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
     tm.st = st;
     HIPCHK(launch_divtab(tab32, tab64, tabN, st));
     if (work) HIPCHK(launch_fill_u32((uint32_t *)work, 2 * kWorkSlots, 0u, st));
+    const bool check = check_dem && d_out;
+    if (check) {
+        HIPCHK(launch_fill_u32(bad, 1, 0u, st));
+        HIPCHK(launch_check_dem(d_dem, (int64_t)H * W, bad, st));
+    }
     if (needT) {
         HIPCHK(tm.begin(0));
         HIPCHK(launch_transpose(d_dem, demT, H, W, st));
@@ -475,6 +484,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
         if (stats)
             for (int k = c.k0; k < c.k1; ++k) count_sector(S[k], evals, pairs);
     }
+    if (check) HIPCHK(launch_poison(d_out, (int64_t)H * W, bad, st));
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         if (!tm.ev.empty()) HIPCHK(hipEventSynchronize(tm.ev.back()));
@@ -680,7 +690,7 @@ size_t total_scratch_bytes(int H, int W, double dx, int n, double R, uint32_t fl
     const size_t tab = (size_t)std::max(H, W) * (sizeof(float2) + sizeof(double2));
     const size_t kahan = (flags & TVS_FLAG_ACC_KAHAN32) ? (size_t)H * W * 2 * sizeof(float) : 0;
     const size_t demT = (fused && n >= 2) ? (size_t)H * W * sizeof(float) : 0;
-    return tab + kahan + demT + 256 * 4 + 64 * 8 + maxChunk + 7 * 256;
+    return tab + kahan + demT + 256 * 4 + 64 * 8 + 256 + maxChunk + 8 * 256;
 }
 
 }  // namespace host
@@ -728,7 +738,7 @@ int tvs_total_viewshed_noalloc(const float *d_dem, int32_t rows, int32_t cols, d
     void *base = nullptr;
     if ((rc = noalloc_base(&base))) return rc;
     return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, 0u, nullptr,
-                     (hipStream_t)hip_stream, -1, nullptr, nullptr, 0, base, TVS_NOALLOC_SCRATCH_BYTES);
+                     (hipStream_t)hip_stream, -1, nullptr, nullptr, 0, base, TVS_NOALLOC_SCRATCH_BYTES, true);
 }
 
 int tvs_abi_version(void) { return TVS_ABI_VERSION; }
@@ -744,7 +754,7 @@ int tvs_total_viewshed_ex(const float *d_dem, int32_t rows, int32_t cols, double
     if (rc) return rc;
     if (int rc2 = check_flags(flags, true)) return rc2;
     return run_total(d_dem, rows, cols, spacing, obs_height, n_sectors, max_dist, d_out, flags, stats,
-                     (hipStream_t)hip_stream, -1, nullptr, nullptr);
+                     (hipStream_t)hip_stream, -1, nullptr, nullptr, 0, nullptr, 0, true);
 }
 
 int tvs_total_viewshed_async(const float *d_dem, int32_t rows, int32_t cols, double spacing, double obs_height,
@@ -947,7 +957,7 @@ int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_se
     for (int t = 0; t < ntiles; ++t) {
         const tvs_tile &T = tiles[t];
         if (int rc = run_total(T.d_dem, T.rows, T.cols, T.spacing, T.obs_height, n_sectors, T.max_dist, T.d_out,
-                               flags, nullptr, (hipStream_t)hip_stream, -1, nullptr, nullptr))
+                               flags, nullptr, (hipStream_t)hip_stream, -1, nullptr, nullptr, 0, nullptr, 0, true))
             return rc;
     }
     return TVS_OK;

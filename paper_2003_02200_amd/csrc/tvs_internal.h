@@ -108,6 +108,10 @@ hipError_t launch_singular(const ChunkArgs &a, const float *dem, uint32_t *rayV,
 hipError_t launch_singular_sum(const ChunkArgs &a, const uint32_t *rayV, double *area, int first,
                                hipStream_t st);
 hipError_t launch_fill_u32(uint32_t *p, int64_t n, uint32_t v, hipStream_t st);
+// *bad |= 1 when an elevation breaks the host entry points' rule (non-finite, or nonzero below 2^-60 m);
+// launch_poison then fills the n map cells with NaN if *bad is set.
+hipError_t launch_check_dem(const float *dem, int64_t n, uint32_t *bad, hipStream_t st);
+hipError_t launch_poison(double *out, int64_t n, const uint32_t *bad, hipStream_t st);
 // Batched path: a fused relocate + sweep over a chunk's (tile, sector, row) items (persistent with a
 // counter, else one workgroup per item), then one back-projection launch over every tile of the
 // chunk. launch_sweep_batch with grid == 0 only prepares the kernel's LDS limit.

@@ -206,6 +206,29 @@ __global__ void k_divtab(float2 *tab32, double2 *tab64, int n) {
     tab64[i] = make_double2(md, __ddiv_rn(1.0, md));
 }
 
+// *bad |= 1 when some elevation is not finite, or is nonzero but below 2^-60 m in magnitude (the rule
+// the host entry points check on the host: biased exponent 255, or below 127 - 60 with a nonzero value).
+__global__ __launch_bounds__(256) void k_check_dem(const float *__restrict__ dem, int64_t n, uint32_t *bad) {
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    bool b = false;
+    for (int64_t x = i0; x < n; x += stride) {
+        const uint32_t u = __float_as_uint(dem[x]);
+        const uint32_t e = (u >> 23) & 0xFFu;
+        b |= e == 0xFFu || (e < 67u && (u & 0x7FFFFFFFu) != 0u);
+    }
+    if (__builtin_amdgcn_ballot_w64(b) && (threadIdx.x & 63) == 0) atomicOr(bad, 1u);
+}
+
+// Every cell of the map becomes NaN when *bad is set: the asynchronous entry points cannot return a
+// status for what they find on the device.
+__global__ __launch_bounds__(256) void k_poison(double *__restrict__ out, int64_t n, const uint32_t *bad) {
+    if (*bad == 0u) return;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = i0; x < n; x += stride) out[x] = __builtin_nan("");
+}
+
 __global__ void k_fill_u32(uint32_t *p, int64_t n, uint32_t v) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1472,6 +1495,18 @@ hipError_t launch_divtab(float2 *tab32, double2 *tab64, int n, hipStream_t st) {
 
 hipError_t launch_transpose(const float *dem, float *demT, int H, int W, hipStream_t st) {
     k_transpose<<<dim3((W + 63) / 64, (H + 63) / 64), 256, 0, st>>>(dem, demT, H, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_dem(const float *dem, int64_t n, uint32_t *bad, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    k_check_dem<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, st>>>(dem, n, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_poison(double *out, int64_t n, const uint32_t *bad, hipStream_t st) {
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    k_poison<<<(unsigned)std::max<int64_t>(blocks, 1), 256, 0, st>>>(out, n, bad);
     return hipGetLastError();
 }
 

@@ -286,6 +286,33 @@ def test_double_rows_beyond_lds_streamed(tvs, orc, H, W, n, R, k):
     assert st.sweep_evals_done == st.los_evals  # the streamed pieces walk every target in range
 
 
+@pytest.mark.parametrize("bad", [float("nan"), float("inf"), -float("inf"), 1e-30, -2e-25])
+def test_device_grid_checked_on_device(tvs, bad):
+    """Entry points that take device grids check the elevations on the device: a non-finite value, or a
+    nonzero one below 2^-60 m, turns the whole map into NaN (the status cannot report it); the same grid
+    without that cell gives a finite map."""
+    import torch
+
+    dem = fractal_dem(70, 3, 0.6, 400.0)[:50, :70].copy()
+    good = torch.from_numpy(dem).cuda()
+    dem[17, 33] = np.float32(bad)
+    d = torch.from_numpy(dem).cuda()
+    note(f"device grid check bad={bad}")
+    ok = tvs.total_viewshed(good, 10.0, 1.5, 8, 300.0)
+    assert bool(torch.isfinite(ok).all())
+    for out in (tvs.total_viewshed(d, 10.0, 1.5, 8, 300.0), tvs.total_viewshed_noalloc(d, 10.0, 1.5, 8, 300.0)):
+        torch.cuda.synchronize()
+        assert bool(torch.isnan(out).all())
+    o = torch.zeros((50, 70), dtype=torch.float64, device="cuda")
+    tvs.total_viewshed_tiles([(d, o, 10.0, 1.5, 300.0)], 8)
+    torch.cuda.synchronize()
+    assert bool(torch.isnan(o).all())
+    # the host entry point rejects the same grid before any work
+    with pytest.raises(tvs.TvsError) as ei:
+        tvs.total_viewshed(dem, 10.0, 1.5, 8, 300.0)
+    assert ei.value.status == -1
+
+
 @pytest.mark.parametrize("H,W,n,R,kind", EXIT_CASES[:3])
 def test_evaluation_counts(tvs, H, W, n, R, kind):
     """The sweep's own count of evaluations: the closed form without the early exit (and for the
