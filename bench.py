@@ -41,15 +41,18 @@ def log(*a):
 
 
 def kernel_source_digest():
-    """Hash of the code of every library source (kernels, launch plan and host code all change the
-    bytes a launch moves), without its // comments and blank lines, so that edits to comments keep
-    a traffic summary valid. The sources hold no "//" inside string literals."""
+    """Hash of the code of every library source the single-grid step runs (kernels, launch plan and
+    host code all change the bytes a launch moves; the request server's file is not on that path),
+    without its // comments and blank lines, so that edits to comments keep a traffic summary valid.
+    The sources hold no "//" inside string literals."""
     import glob
     import hashlib
 
     h = hashlib.sha256()
     for path in sorted(glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.h")) +
                        glob.glob(os.path.join(ROOT, "paper_2003_02200_amd", "csrc", "*.hip"))):
+        if os.path.basename(path) == "tvs_server.hip":
+            continue
         h.update(os.path.basename(path).encode())
         for line in open(path, encoding="utf-8"):
             code = line.split("//", 1)[0].rstrip()
@@ -543,8 +546,8 @@ def bench_serve(args, seconds, cold=False, standalone=False):
         srv.close()
         return res, wall, st
 
-    def pct(res, kind=None):
-        v = np.array([r.latency_ms for r, q in zip(res, reqs) if kind is None or q[1] == kind])
+    def pct(res, kind=None, field="latency_ms"):
+        v = np.array([getattr(r, field) for r, q in zip(res, reqs) if kind is None or q[1] == kind])
         return (float(np.percentile(v, 50)), float(np.percentile(v, 99))) if len(v) else (None, None)
 
     res_c = st_c = None
@@ -591,7 +594,8 @@ def bench_serve(args, seconds, cold=False, standalone=False):
                                "80% singular on grids 512..4096, 20% total on grids 256..1024, 10 m, observer 1.5 m, "
                                "180 sectors, max distance = grid extent", "requests": len(reqs)},
         "latency_ms": {"p50": pct(res)[0], "p99": pct(res)[1], "singular_p50": pct(res, "s")[0],
-                       "singular_p99": pct(res, "s")[1], "total_p50": pct(res, "t")[0], "total_p99": pct(res, "t")[1]},
+                       "singular_p99": pct(res, "s")[1], "total_p50": pct(res, "t")[0], "total_p99": pct(res, "t")[1],
+                       "singular_queue_p99": pct(res, "s", "queue_ms")[1]},
         "served_req_per_s": len(reqs) / wall,
         "capacity_req_per_s": len(reqs) / wall_f,
         "plain_one_at_a_time_req_per_s": len(reqs) / plain,

@@ -538,7 +538,7 @@ int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, i
     const size_t host_bytes = sz_ent + sz_bt + sz_items;
     if (stage.cap < host_bytes) {
         const size_t want = std::max(host_bytes, (size_t)2 * stage.cap);
-        if (stage.p) (void)hipHostFree(stage.p);
+        if (stage.p) stage.retired.push_back(stage.p);
         stage.p = nullptr;
         stage.cap = 0;
         HIPCHK(hipHostMalloc(&stage.p, want, hipHostMallocDefault));

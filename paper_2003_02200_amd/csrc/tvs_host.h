@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/libtvs.h"
 #include "tvs_geom.h"
 
@@ -81,10 +83,13 @@ void tune_store(const TuneKey &k, int a, int b);
 const char *source_hash();
 int ceil_log2(int64_t v);
 
-// Pinned host staging owned by a caller of batch_enqueue (grown there, freed by the owner).
+// Pinned host staging owned by a caller of batch_enqueue (grown there, freed by the owner). A grown
+// buffer leaves the old one in `retired` rather than freeing it, because freeing pinned memory waits
+// for the whole device; the owner frees both at its end.
 struct PinnedStaging {
     void *p = nullptr;
     size_t cap = 0;
+    std::vector<void *> retired;
 };
 // Do the skewed rows of grids with sides up to maxWx fit the batched sweep's LDS?
 bool batch_rows_fit(int maxWx, bool f64);

@@ -1670,7 +1670,9 @@ hipError_t launch_sweep_batch(const BatchEnt *ent, const uint32_t *items, int ni
                               uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool rcp,
                               int waves, int grid, int maxWx, int maxK, unsigned long long *work,
                               hipStream_t st) {
-    // the same choice as launch_sweep's, so a tile's rows take the same steps in either path
+    // The rule is launch_sweep's, applied to the bucket's longest row and line of sight rather than to
+    // one grid's chunk, so a tile's rows may prune with another table here than in the single-grid path
+    // (and count other evaluations); both prunings are exact, so the maps are the same.
     int rmq = 0, slide = 0;
     const size_t lds = sweep_lds_launch(maxWx, f64, maxK, rmq, slide);
 #define TVS_BATCH_GO(TZ, NW, RCP, SL, TAB)                                                              \

@@ -4,12 +4,13 @@
 // requests from any thread; one scheduler thread owns the device work:
 //  - total requests are admitted in arrival order while their device memory (output maps plus
 //    scratch) fits the HBM budget. Whenever one of two group slots is free, the waiting totals
-//    (same sector count and precision, up to a group limit) leave together as one batch: one
-//    persistent fused relocate + sweep launch over every (request, sector, skewed row) item and
-//    one back-projection launch per sector chunk, on the slot's stream; requests that arrive while
-//    both groups run gather into the next group. Totals the batched sweep does not take (float
-//    Kahan sums, the lane-per-target sweep, the full walk, rows longer than the LDS) run alone on
-//    the next of several streams, overlapping with the rest;
+//    (same sector count and precision, up to a group limit) leave together as one batch on the
+//    slot's stream: per sector chunk, one gather + sweep launch per size bucket with one workgroup
+//    per (request, sector, skewed row) item, so that singular work started later interleaves with
+//    it, and one back-projection launch; requests that arrive while both groups run gather into the
+//    next group. Totals the batched sweep does not take (float Kahan sums, the lane-per-target
+//    sweep, the full walk, rows longer than the LDS) run alone on the next of several streams,
+//    overlapping with the rest;
 //  - singular requests that are waiting are launched together: one multi-query ray-scan launch
 //    (every line of sight of every query, one wavefront each) and one per-query area sum, up to a
 //    batch limit, as soon as the previous singular batch has finished;
@@ -123,6 +124,7 @@ struct tvs_server {
     uint64_t next_ticket = 1;
     SingBatch sb[2];
     TotGroup tg[2];
+    std::vector<void *> retired_host;  // outgrown pinned staging, freed at the end
     int64_t n_done = 0, n_batches = 0, n_batched = 0, max_running = 0, n_tbatches = 0, n_tbatched = 0;
     bool stop = false;
     int fatal = TVS_OK;
@@ -141,14 +143,17 @@ size_t total_bytes(const tvs_server *s, const Grid &g, const Request *r) {
            total_scratch_bytes(g.rows, g.cols, g.spacing, r->n, r->R, r->flags, cap);
 }
 
-int grow_batch(SingBatch &b, size_t secs, size_t nq) {
+// Sizes a singular slot's staging for `secs` sectors and `nq` queries. The server sizes both slots
+// at its start for a full batch of 180-sector queries; a later growth never waits for the device:
+// the old pinned buffers are kept until the server ends (freeing pinned memory waits for every
+// stream) and the device tables move through the slot's stream-ordered pool.
+int grow_batch(tvs_server *s, SingBatch &b, size_t secs, size_t nq) {
     if (secs <= b.cap_secs && nq <= b.cap_q) return TVS_OK;
     secs = std::max(secs, b.cap_secs * 2);
     nq = std::max(nq, b.cap_q * 2);
-    if (b.h_secs) (void)hipHostFree(b.h_secs);
-    if (b.h_q) (void)hipHostFree(b.h_q);
-    if (b.h_area) (void)hipHostFree(b.h_area);
-    if (b.d_mem) (void)hipFree(b.d_mem);
+    for (void *p : {(void *)b.h_secs, (void *)b.h_q, (void *)b.h_area})
+        if (p) s->retired_host.push_back(p);
+    if (b.d_mem) (void)hipFreeAsync(b.d_mem, s->sing_stream);
     b.h_secs = nullptr;
     b.h_q = nullptr;
     b.h_area = nullptr;
@@ -159,7 +164,7 @@ int grow_batch(SingBatch &b, size_t secs, size_t nq) {
     HIPCHK(hipHostMalloc((void **)&b.h_area, nq * sizeof(double), hipHostMallocDefault));
     const size_t a = align256(secs * sizeof(SingSec)), q = align256(nq * sizeof(SingQuery)),
                  rays = align256(2 * secs * sizeof(uint32_t)), ar = align256(nq * sizeof(double));
-    HIPCHK(hipMalloc((void **)&b.d_mem, a + q + rays + ar));
+    HIPCHK(hipMallocAsync((void **)&b.d_mem, a + q + rays + ar, s->sing_stream));
     b.d_secs = (SingSec *)b.d_mem;
     b.d_q = (SingQuery *)(b.d_mem + a);
     b.d_rays = (uint32_t *)(b.d_mem + a + q);
@@ -184,7 +189,7 @@ int launch_singular_batch(tvs_server *s, SingBatch &b) {
             ++it;
         }
     }
-    if (int rc = grow_batch(b, secs, b.reqs.size())) return rc;
+    if (int rc = grow_batch(s, b, secs, b.reqs.size())) return rc;
     size_t k0 = 0;
     for (size_t qi = 0; qi < b.reqs.size(); ++qi) {
         Request *r = b.reqs[qi];
@@ -472,12 +477,20 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
     tvs_server *s = new (std::nothrow) tvs_server;
     if (!s) return fail(TVS_ENOMEM, "host memory for the server");
     auto bail = [&](int rc) {
+        for (SingBatch &b : s->sb) {
+            if (b.ev) (void)hipEventDestroy(b.ev);
+            for (void *p : {(void *)b.h_secs, (void *)b.h_q, (void *)b.h_area})
+                if (p) (void)hipHostFree(p);
+            if (b.d_mem) (void)hipFreeAsync(b.d_mem, s->sing_stream);
+        }
+        for (void *p : s->retired_host) (void)hipHostFree(p);
+        for (TotGroup &G : s->tg) {
+            if (G.ev) (void)hipEventDestroy(G.ev);
+            if (G.stage.p) (void)hipHostFree(G.stage.p);
+        }
+        if (s->sing_stream) (void)hipStreamSynchronize(s->sing_stream);
         for (hipStream_t st : s->streams) (void)hipStreamDestroy(st);
         if (s->sing_stream) (void)hipStreamDestroy(s->sing_stream);
-        for (SingBatch &b : s->sb)
-            if (b.ev) (void)hipEventDestroy(b.ev);
-        for (TotGroup &G : s->tg)
-            if (G.ev) (void)hipEventDestroy(G.ev);
         delete s;
         return rc;
     };
@@ -489,14 +502,16 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
     s->max_batch = c.max_singular_batch > 0 ? c.max_singular_batch : 64;
     s->max_total_batch = c.max_total_batch > 0 ? c.max_total_batch : 16;
     pool_keep_memory(s->dev);
+    // the singular stream first: streams beyond the hardware queues share one, and the first created
+    // is the least likely to share with a long total
+    if (hipStreamCreateWithFlags(&s->sing_stream, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(TVS_EDEVICE, "stream creation failed"));
     for (int x = 0; x < s->nstreams; ++x) {
         hipStream_t st;
         if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess)
             return bail(fail(TVS_EDEVICE, "stream creation failed"));
         s->streams.push_back(st);
     }
-    if (hipStreamCreateWithFlags(&s->sing_stream, hipStreamNonBlocking) != hipSuccess)
-        return bail(fail(TVS_EDEVICE, "stream creation failed"));
     for (SingBatch &b : s->sb)
         if (hipEventCreateWithFlags(&b.ev, hipEventDisableTiming) != hipSuccess)
             return bail(fail(TVS_EDEVICE, "event creation failed"));
@@ -505,6 +520,18 @@ int tvs_server_create(const tvs_server_config *cfg, tvs_server **out) {
         G.stream = x % s->nstreams;
         if (hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess)
             return bail(fail(TVS_EDEVICE, "event creation failed"));
+    }
+    // Staging sized up front (a full batch of 180-sector singular queries; 8 MB of work lists per
+    // group of totals), so that serving seldom grows it.
+    for (SingBatch &b : s->sb)
+        if (int rc = grow_batch(s, b, (size_t)s->max_batch * 180, (size_t)s->max_batch)) return bail(rc);
+    for (TotGroup &G : s->tg) {
+        const size_t want = (size_t)8 << 20;
+        if (hipHostMalloc(&G.stage.p, want, hipHostMallocDefault) != hipSuccess) {
+            G.stage.p = nullptr;
+            return bail(fail(TVS_ENOMEM, "pinned staging of %zu bytes", want));
+        }
+        G.stage.cap = want;
     }
     s->worker = std::thread(scheduler, s);
     *out = s;
@@ -710,14 +737,17 @@ int tvs_server_destroy(tvs_server *s) {
     for (TotGroup &G : s->tg) {
         if (G.ev) (void)hipEventDestroy(G.ev);
         if (G.stage.p) (void)hipHostFree(G.stage.p);
+        for (void *p : G.stage.retired) (void)hipHostFree(p);
     }
     for (SingBatch &b : s->sb) {
         if (b.ev) (void)hipEventDestroy(b.ev);
         if (b.h_secs) (void)hipHostFree(b.h_secs);
         if (b.h_q) (void)hipHostFree(b.h_q);
         if (b.h_area) (void)hipHostFree(b.h_area);
-        if (b.d_mem) (void)hipFree(b.d_mem);
+        if (b.d_mem) (void)hipFreeAsync(b.d_mem, s->sing_stream);
     }
+    for (void *p : s->retired_host) (void)hipHostFree(p);
+    if (s->sing_stream) (void)hipStreamSynchronize(s->sing_stream);
     for (Grid &g : s->grids) {
         (void)hipFree(g.d);
         (void)hipFree(g.dT);
