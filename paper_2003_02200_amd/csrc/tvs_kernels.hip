@@ -423,6 +423,8 @@ __global__ __launch_bounds__(256) void k_relocate(const ChunkArgs a, const float
 // Levels of the early exit's range-maximum table: windows of 1, 2, .., 32 blocks of 32 samples,
 // answering the maximum over any 1..64 consecutive blocks with two reads.
 constexpr int RMQ_LEVELS = 6;
+// Entries of the sliding maxima beyond each end of the row (copies of the end entries).
+constexpr int SLIDE_PAD = 8;
 
 // Ring sums of 32 visibility bits: step m0+s lands in bit 31-s, so the ring weight 2m+1 of set
 // bit b is (2 m0 + 63) - 2b, and sum_b b = sum_k 2^k popc(bits & M_k).
@@ -463,11 +465,11 @@ struct RingAcc {
 // With SLIDE (the number of table levels, 0 without) the skip test reads the sliding maxima `slide`
 // instead of the table's level 1, and the launch keeps every exit range within the table (there is
 // no `bnd`).
-template <typename Tz, int DIR, bool RCP, bool PRUNE, int SLIDE>
+template <typename Tz, int DIR, bool RCP, bool PRUNE, int SLIDE, bool COUNT>
 __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
                                               const typename Tab<Tz>::type *__restrict__ tab, uint32_t &U,
                                               const Tz *bnd, const float *rmq, int nb, int bfar, int pbase,
-                                              int q, bool live, int own, bool count, int &done, int &skipped,
+                                              int q, bool live, int own, int &done, int &skipped,
                                               const float *slide) {
     // a lane past the row end starts with a +inf horizon: it never sees a target and never
     // holds back the early exit (its sums are discarded)
@@ -508,15 +510,19 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     // the wavefront skips steps mm .. mm + 31: none of their targets can be visible on any lane.
     // A lane's 32 targets lie in two consecutive blocks, whose maximum is level 1 of the table;
     // with SLIDE, in the 40 samples from the 8-aligned position at or before the first, whose
-    // maximum is slide[first >> 3] (indices clamped to the row: a clamped entry still covers
-    // every target inside it, beyond it lie -inf sentinels, and a lane past the row end has a
-    // +inf horizon).
+    // maximum is slide[first >> 3]. Steps mm = 1 + 32 k put that entry 4 k after (DIR > 0) or
+    // before (DIR < 0) the lane's entry for mm = 1, so the lane keeps a pointer to that one and a
+    // test adds a uniform offset. Entries beyond the row's hold its end entries: the indices stay
+    // within 8 of the row's (a lane's reads lie inside its sentinels), an end entry still covers
+    // every target inside it, beyond it lie -inf sentinels, and a lane past the row end has a +inf
+    // horizon.
+    const float *sl = SLIDE != 0 ? slide + ((DIR > 0 ? q + 1 : q - 32) >> 3) : nullptr;
     auto block_hidden = [&](int mm) -> bool {
-        const int first = DIR > 0 ? q + mm : q - mm - 31;  // the lane's lowest target position
         float zf;
         if constexpr (SLIDE != 0) {
-            zf = slide[min(max(first >> 3, 0), 4 * nb - 1)];
+            zf = sl[DIR * ((mm - 1) >> 3)];
         } else {
+            const int first = DIR > 0 ? q + mm : q - mm - 31;  // the lane's lowest target position
             const int b = min(max(first >> 5, 0), nb - 1);
             zf = rmq[nb + b];
         }
@@ -526,21 +532,21 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
     uint32_t bits = 0;
     int m = 1;
     bool stop = false;
-    bool test = true;  // after a block in which half the lanes saw a target the next is not tested
+    int busy = 0;  // lanes that saw a target in the last block: from 32 on, the next is not tested
     skipped = 0;
     for (; m + 31 <= mfull; m += 32) {
         if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads on the scalar path
         // The exit test passing implies the skip test passing (its blocks lie inside the exit's
         // range and its steps inside the remaining ones), so the exit is tested only for blocks
         // that can be skipped; a block that must be evaluated costs one test.
-        if (PRUNE && m > 1 && (!rmq || (test && block_hidden(m)))) {
+        if (PRUNE && m > 1 && (!rmq || (busy < 32 && block_hidden(m)))) {
             if (hidden_from(m)) {
                 stop = true;
                 break;
             }
             if (rmq) {
                 // no horizon moves and no bit is set: the block changes nothing
-                if (count) skipped += max(0, min(own, m + 31) - m + 1);
+                if (COUNT) skipped += max(0, min(own, m + 31) - m + 1);
                 continue;
             }
         }
@@ -551,7 +557,8 @@ __device__ __forceinline__ uint32_t sweep_dir(const Tz *zp, Tz h, int mb, int K,
         // most blocks see nothing on any lane, and skip the ring sums.
         const unsigned long long seen = __builtin_amdgcn_ballot_w64(bits != 0u);
         if (seen) ra.add(bits, m);
-        test = __popcll(seen) < 32;  // skipping a test only evaluates a block it might have skipped
+        // skipping a test only evaluates a block it might have skipped
+        busy = __builtin_amdgcn_readfirstlane((int)__popcll(seen));
     }
     if (PRUNE && !stop && m > 1 && m <= mb) stop = hidden_from(m);
     uint32_t acc = ra.total();
@@ -629,6 +636,12 @@ __device__ void block_bounds(const Tz *z, int nb, Tz *suf, Tz *pre, float *rmq, 
     constexpr int NLEV = SLIDE ? SLIDE : RMQ_LEVELS;
     if constexpr (SLIDE != 0) {
         sliding_max40(z, nb, slide, rmq);  // the table's first level from its groups of 8
+        // SLIDE_PAD copies of each end entry on either side (sliding_max40 ends with a barrier)
+        if (threadIdx.x < 2 * SLIDE_PAD) {
+            const int x = threadIdx.x, n8 = nb << 2;
+            const float v = x < SLIDE_PAD ? slide[0] : slide[n8 - 1];
+            slide[x < SLIDE_PAD ? x - SLIDE_PAD : n8 + x - SLIDE_PAD] = v;
+        }
     } else {
         for (int b = threadIdx.x; b < nb; b += blockDim.x) {
             Tz m = z[32 * b];
@@ -748,13 +761,13 @@ __device__ __forceinline__ int load_row(const ChunkArgs &a, const RowSrc &src, c
 
 // Sweeps a skewed row of nt samples held in LDS (row[TVS_SWEEP_PAD + q], -inf sentinels on both
 // sides, room for the early exit's block maxima after them) and stores U | e << 30 of POV q at
-// dst[q]. Returns the evaluations this lane carried out when `count` is set. After the row lie
+// dst[q]. Returns the evaluations this lane carried out when COUNT is set. After the row lie
 // the suffix and prefix block maxima, then (use_rmq) the range-maximum table; with SLIDE the
 // table of SLIDE levels, then the sliding maxima of 40 samples at every 8th position.
-template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE = 0>
+template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE, bool COUNT>
 __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                               const typename Tab<Tz>::type *__restrict__ tab,
-                                              uint32_t *__restrict__ dst, bool count, bool use_rmq) {
+                                              uint32_t *__restrict__ dst, bool use_rmq) {
     const int nb = (nt + 31) >> 5;
     Tz *suf = nullptr, *pre = nullptr;
     float *rmq, *slide = nullptr;
@@ -762,7 +775,7 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         // launches with SLIDE set use_rmq; a pointer the compiler cannot prove non-null keeps the
         // block loop's ring sums in place (proven, its loop copies them on every block)
         rmq = use_rmq ? reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) : nullptr;
-        slide = reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) + SLIDE * nb;
+        slide = reinterpret_cast<float *>(row + nt + 2 * TVS_SWEEP_PAD) + SLIDE * nb + SLIDE_PAD;
     } else {
         suf = row + nt + 2 * TVS_SWEEP_PAD;
         pre = suf + nb;
@@ -789,12 +802,12 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         const int bfar_f = min(nb - 1, (q0 + 63 + Kc) >> 5), bfar_b = max(0, q0 - Kc) >> 5;
         const int own_f = min(K, nt - 1 - q), own_b = min(K, q);  // this lane's last step each way
         int sf, sb;
-        e += sweep_dir<Tz, +1, RCP, PRUNE, SLIDE>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, q, live,
-                                                  own_f, count, df, sf, slide);
-        e += sweep_dir<Tz, -1, RCP, PRUNE, SLIDE>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, q, live,
-                                                  own_b, count, db, sb, slide);
+        e += sweep_dir<Tz, +1, RCP, PRUNE, SLIDE, COUNT>(zp, h, fwd, K, tab, U, suf, rmq, nb, bfar_f, q0, q, live,
+                                                         own_f, df, sf, slide);
+        e += sweep_dir<Tz, -1, RCP, PRUNE, SLIDE, COUNT>(zp, h, bwd, K, tab, U, pre, rmq, nb, bfar_b, top, q, live,
+                                                         own_b, db, sb, slide);
         if (live) dst[q] = U | (e << 30);
-        if (count && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
+        if (COUNT && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
     }
     return evals;
 }
@@ -824,11 +837,14 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowS
     int jlo;
     const int nt = load_row<Tz>(a, src, s, ri, skw, row, jlo);
     if (nt == 0) return;
-    if (work && threadIdx.x == 0) wg_work = 0;
-    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE, SLIDE>(row, nt, s.K, h0_of<Tz>(a), tab,
-                                                                V + skw_row(s, s.t0 + ri, a.pitch) + jlo,
-                                                                work != nullptr, a.rmq != 0);
-    if (work) add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
+    uint32_t *dst = V + skw_row(s, s.t0 + ri, a.pitch) + jlo;
+    if (!work) {
+        sweep_row<Tz, NW, RCP, PRUNE, SLIDE, false>(row, nt, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0);
+        return;
+    }
+    if (threadIdx.x == 0) wg_work = 0;
+    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE, SLIDE, true>(row, nt, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0);
+    add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
 // ---------------------------------------------------------- rows longer than the LDS holds
@@ -983,10 +999,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         int Hx, Wx;
         frame_dims(E.s.kase, E.H, E.W, Hx, Wx);
         const int nt = gather_row<Tz>(frame_ref(E.s.kase, E.H, E.W, E.dem, E.demT), Hx, Wx, E.s, ri, row, jlo);
-        if (nt > 0)
-            evals += sweep_row<Tz, NW, RCP, true, SLIDE>(row, nt, E.s.K, h0_of<Tz>(E), tab,
-                                                         V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo,
-                                                         work != nullptr, rmq != 0);
+        uint32_t *dst = V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo;
+        if (nt > 0 && !work) sweep_row<Tz, NW, RCP, true, SLIDE, false>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0);
+        if (nt > 0 && work) evals += sweep_row<Tz, NW, RCP, true, SLIDE, true>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0);
         __syncthreads();  // the row is read by every wavefront before the next gather
     }
     if (work) add_work(work, wg_work, evals, blockIdx.x);
@@ -1478,7 +1493,7 @@ static size_t sweep_lds_launch(int maxWx, bool f64, int maxK, int &rmq, int &sli
     if (rmq && maxK <= SLIDE_MAX_K_LONG) {
         const int lev = maxK <= SLIDE_MAX_K ? RMQ_LEVELS : RMQ_LEVELS + 1;
         const size_t bytes = (size_t)(maxWx + 2 * TVS_SWEEP_PAD) * (f64 ? sizeof(double) : sizeof(float)) +
-                             (size_t)(lev + 4) * nbx * sizeof(float);
+                             ((size_t)(lev + 4) * nbx + 2 * SLIDE_PAD) * sizeof(float);
         auto resident = [](size_t b) { return std::min<size_t>((160 * 1024) / (b + 64), 8); };
         if (bytes + 64 <= (size_t)cap && resident(bytes) >= resident(full)) {
             slide = lev;
