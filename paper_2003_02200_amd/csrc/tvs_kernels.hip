@@ -781,13 +781,21 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
         pre = suf + nb;
         rmq = use_rmq ? reinterpret_cast<float *>(pre + nb) : nullptr;
     }
-    if (PRUNE) block_bounds<Tz, SLIDE>(row + TVS_SWEEP_PAD, nb, suf, pre, rmq, slide);
+    // Segments of 64 POVs go to the wavefronts as they free up, middle of the row first (its POVs have
+    // lines of sight both ways): their costs differ widely, and the workgroup holds its LDS until its
+    // last wavefront ends. The k-th segment handed out is c, c + 1, c - 1, c + 2, ... (a permutation of
+    // 0 .. nseg - 1).
+    __shared__ int seg_next;
+    if (threadIdx.x == 0) seg_next = NW;
+    if (PRUNE) block_bounds<Tz, SLIDE>(row + TVS_SWEEP_PAD, nb, suf, pre, rmq, slide);  // ends with a barrier
+    else __syncthreads();
     const int Kc = min(K, nt);  // K may be unbounded
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int nseg = (nt + 63) >> 6;
     uint32_t evals = 0;
-    for (int sg = wv; sg < nseg; sg += NW) {
+    for (int k = wv; k < nseg;) {
+        const int c = (nseg - 1) >> 1, sg = (k & 1) ? c + ((k + 1) >> 1) : c - (k >> 1);  // middle-out
         const int q0 = sg << 6;
         const int q = q0 + lane;
         const bool live = q < nt;
@@ -808,6 +816,9 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                                          own_b, db, sb, slide);
         if (live) dst[q] = U | (e << 30);
         if (COUNT && live) evals += (uint32_t)(min(df, own_f) - sf + min(db, own_b) - sb);
+        int nx = 0;
+        if (lane == 0) nx = atomicAdd(&seg_next, 1);
+        k = __builtin_amdgcn_readfirstlane(nx);
     }
     return evals;
 }
