@@ -132,7 +132,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        log("bench.py measures one GPU only: this build has no multi-GPU path "
+        log("bench.py measures one GPU only: the library has no multi-GPU path "
             "(sectors would shard across GPUs with one final reduce; see the design notes). Run with --gpus 1.")
         sys.exit(2)
 
@@ -255,7 +255,7 @@ def bench_single(args):
 
     # the relocation as its own kernel (TVS_FLAG_RELOCATE), measured outside the timed region: its
     # algorithmic bytes per existing sample are 4 read + 4 written for a float skwDEM (the paper's), and
-    # 4 + 8 as this build writes it (double elevations)
+    # 4 + 8 as the library writes it (double elevations)
     relocation = None
     if args.flags == 0:
         tvs.total_viewshed(d, *call, flags=tvs.FLAG_RELOCATE)
