@@ -222,8 +222,8 @@ typedef struct tvs_batch_info {
     int32_t tiles;
     int32_t chunks;           /* sector groups, each one sweep and one back-projection launch */
     int32_t kernel_launches;  /* kernels in the captured graph */
-    int32_t waves_per_group;  /* launch shape of the persistent sweep */
-    int32_t groups;           /* workgroups of the persistent sweep */
+    int32_t waves_per_group;  /* launch shape of bucket 0's sweep (tvs_batch_get_bucket for the others) */
+    int32_t groups;           /* its workgroups per launch (persistent), or 0 (one per skewed row) */
     int32_t tuned;            /* 1 if the shape came from timing candidates */
     int64_t los_evals;        /* closed-form line-of-sight evaluations of one pass */
     int64_t pov_sector_pairs;
@@ -250,10 +250,11 @@ typedef struct tvs_batch_bucket {
     int64_t items;            /* (tile, sector, skewed row) items over all chunks */
 } tvs_batch_bucket;
 
-/* Plans a batch: validates every tile, groups the sectors into chunks within the scratch budget,
- * uploads the work lists and captures one pass (per chunk: one persistent fused relocate + sweep
- * launch over every (tile, sector, skewed row) item, then one back-projection launch over every
- * tile) into a HIP graph. The DEM and output buffers are bound to the batch: they must stay
+/* Plans a batch: validates every tile, groups the sectors into chunks within the scratch budget and
+ * the tiles into buckets, uploads the work lists and captures one pass into a HIP graph: one
+ * transposition per tile, then per chunk one fused relocate + sweep launch per bucket over its
+ * (tile, sector, skewed row) items (persistent workgroups or one workgroup per item, as the bucket's
+ * shape says) and one back-projection launch over every tile. The DEM and output buffers are bound to the batch: they must stay
  * allocated and in place until tvs_batch_destroy. Flags: TVS_FLAG_SLOPE_F32, TVS_FLAG_SLOPE_F64,
  * TVS_FLAG_SLOPE_EXACT, TVS_FLAG_COUNT_EVALS, TVS_FLAG_AUTOTUNE. Runs on the current HIP device
  * (synchronously at creation). Section 4.1 steps 1a-1d applied to every tile; the batching,
@@ -284,9 +285,9 @@ int tvs_total_viewshed_tiles(const tvs_tile *tiles, int32_t ntiles, int32_t n_se
  * A scheduler thread admits total requests in arrival order while their device memory (maps plus
  * scratch, scratch capped at a quarter of the budget) fits hbm_budget_bytes. Whenever one of two
  * group slots is free, the waiting total requests of the front request's sector count and flags
- * (up to max_total_batch) leave together as one batch (tvs_batch_create's launches: one persistent
- * fused relocate + sweep launch over every request's skewed rows and one back-projection launch per
- * sector chunk); totals that arrive while both groups run gather into the next group. Totals the
+ * (up to max_total_batch) leave together as one batch (tvs_batch_create's launches, enqueued without a
+ * graph: per sector chunk one fused relocate + sweep launch per bucket, with one workgroup per skewed
+ * row so that singular work started later interleaves, and one back-projection launch); totals that arrive while both groups run gather into the next group. Totals the
  * batched sweep does not take (TVS_FLAG_ACC_KAHAN32, TVS_FLAG_SWEEP_SCAN, TVS_FLAG_NO_PRUNE, rows
  * longer than the LDS holds) run alone on the next of `streams` streams, overlapping with the rest.
  * Waiting singular requests are launched together, up to max_singular_batch per launch (one

@@ -94,8 +94,8 @@ struct PinnedStaging {
 // Do the skewed rows of grids with sides up to maxWx fit the batched sweep's LDS?
 bool batch_rows_fit(int maxWx, bool f64);
 // Total viewsheds of independent tiles as one batch enqueued on `st` (no graph): per sector chunk
-// (skewed viewshed rows within `budget` bytes) one fused relocate + sweep launch with a workgroup per
-// (tile, sector, row) item and one back-projection launch over every tile. `demT` (nullable) holds
+// (skewed viewshed rows within `budget` bytes) one fused relocate + sweep launch per bucket of tiles
+// with a workgroup per (tile, sector, row) item and one back-projection launch over every tile. `demT` (nullable) holds
 // each tile's transposed grid, read for the 45..135 deg axes. Flags: the decision precision and slope
 // form (TVS_FLAG_SLOPE_F32, _F64, _EXACT).
 int batch_enqueue(const tvs_tile *tiles, const float *const *demT, int ntiles, int n, uint32_t flags, hipStream_t st,
