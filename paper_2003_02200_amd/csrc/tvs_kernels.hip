@@ -447,9 +447,10 @@ struct RingAcc {
 // One direction of the lines of sight of a wavefront's 64 POVs. `zp` points at each lane's POV in
 // the LDS row; `mb` is the last step any lane of the wavefront needs (lanes whose row ends earlier
 // read -inf sentinels, which are never visible). Steps m < K add the whole ring 2m+1 to U; the
-// step m = K (the ring clipped at rho) is returned as 0/1. Steps run in blocks of 32 sharing one
-// scalar load of the {m, 1/m} table; each step is subtract, slope, compare + add-with-carry into
-// the bit mask, max. Returns in `done` the number of steps taken.
+// step m = K (the ring clipped at rho) is returned as 0/1. Steps run in blocks of 32 whose table
+// entries {m, 1/m} are wave-uniform (scalar loads); each step is subtract, slope, compare +
+// add-with-carry into the bit mask, max. Returns in `done` the number of steps taken and, with
+// COUNT, in `skipped` the lane's steps inside skipped blocks.
 //
 // Early exit (PRUNE): before each block the wavefront stops when no target from step m on can
 // be visible on any live lane. zs bounds every elevation a lane still reads: the maximum over the
