@@ -338,7 +338,8 @@ def bench_single(args):
 
 def cpu_baseline(workload, dem, call):
     """The oracle as it stands on the host cores: the centred 256 x 256 crop of the 2000 x 2000 workload
-    (every POV of the crop walks the whole DEM in every sector), and the full 128 x 128 workload."""
+    (every POV of the crop walks the whole DEM in every sector), the full 128 x 128 workload, and the
+    centred 64 x 64 crop of the 4000 x 4000 precision-study workload (5 m, 360 sectors, 10 km)."""
     import oracle
     from synth import WORKLOADS, workload_dem
 
@@ -354,6 +355,14 @@ def cpu_baseline(workload, dem, call):
     t2 = time.perf_counter()
     _, ev1 = oracle.total(d1, w1["spacing"], w1["obs_height"], w1["n_sectors"], w1["max_dist"], prec=64, count=True)
     s1 = time.perf_counter() - t2
+    w4 = WORKLOADS["tvs4000"]
+    d4 = workload_dem("tvs4000")
+    c4 = 64
+    r4, q4 = (d4.shape[0] - c4) // 2, (d4.shape[1] - c4) // 2
+    t3 = time.perf_counter()
+    _, ev4 = oracle.total(d4, w4["spacing"], w4["obs_height"], w4["n_sectors"], w4["max_dist"], prec=64,
+                          window=(r4, q4, c4, c4), count=True)
+    s4 = time.perf_counter() - t3
     log(f"cpu baseline: {ev_cpu / cpu_s:.3e} evals/s on {oracle.threads()} threads")
     return {
         "value": ev_cpu / cpu_s,
@@ -366,6 +375,8 @@ def cpu_baseline(workload, dem, call):
         "cells_per_s": cw * cw / cpu_s,
         "full_128x128_workload": {"evals": ev1, "seconds": s1, "evals_per_s": ev1 / s1,
                                   "cells_per_s": 128 * 128 / s1},
+        "crop_64x64_of_4000x4000": {"evals": ev4, "seconds": s4, "evals_per_s": ev4 / s4,
+                                      "cells_per_s": c4 * c4 / s4},
     }
 
 
