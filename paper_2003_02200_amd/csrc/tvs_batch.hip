@@ -1,10 +1,9 @@
 // tvs_batch.hip -- total viewsheds of many independent DEM tiles of uneven size as one batch.
 //
 // Each tile is its own total viewshed (Section 4.1 steps 1a-1d); the tiles share the sector
-// count. Per chunk of sectors, one persistent workgroup pool walks the list of every
-// (tile, sector, skewed row) item of every tile -- gathering each skewed row straight from its
-// tile's DEM (the relocation fused into the sweep) -- and one back-projection launch covers all
-// tiles. The whole pass is captured once into a HIP graph and replayed; the work lists live in
+// count. Per chunk of sectors, sweep launches walk the list of every (tile, sector, skewed row)
+// item of every tile -- gathering each skewed row straight from its tile's DEM or its transposed
+// copy (the relocation fused into the sweep) -- and one back-projection launch covers all tiles. The whole pass is captured once into a HIP graph and replayed; the work lists live in
 // device memory and a replay only resets the item counters (with a fill kernel). Tiles are grouped
 // into buckets by the size classes of their longest side and their longest line of sight; each
 // bucket has its own sweep launch per chunk, sized for its rows, and its own launch shape (waves
