@@ -259,6 +259,7 @@ def bench_single(args):
     relocation = None
     if args.flags == 0:
         tvs.total_viewshed(d, *call, flags=tvs.FLAG_RELOCATE)
+        torch.cuda.synchronize()  # the warm call ends before the first timed one starts
         rms = rn = rsteps = 0
         rstep_ms = 0.0
         for _ in range(2):
