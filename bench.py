@@ -104,6 +104,16 @@ def read_counters(path, workload, flags):
         return None
 
 
+def sub_bench(name, fn):
+    """A sub-measurement of the line: its failure is reported in the line (with the error) instead of
+    losing the headline measurement already taken."""
+    try:
+        return fn()
+    except Exception as e:  # noqa: BLE001 - any failure of a sub-measurement is reported, not raised
+        log(f"{name}: failed: {type(e).__name__}: {e}")
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -146,9 +156,9 @@ def main():
         return bench_multiple(args)
     line = bench_single(args)
     if not args.no_serve and args.workload == "tvs2000" and args.flags == 0:
-        line["serve"] = bench_serve(args, 8.0, cold=False)
+        line["serve"] = sub_bench("serve", lambda: bench_serve(args, 8.0, cold=False))
     if not args.no_batch and args.workload == "tvs2000" and args.flags == 0:
-        line["batch"] = bench_batch(args, args.batch_tiles, 2, 1)
+        line["batch"] = sub_bench("batch", lambda: bench_batch(args, args.batch_tiles, 2, 1))
     print(json.dumps(line), flush=True)
 
 
@@ -295,7 +305,7 @@ def bench_single(args):
         host_ms = (time.perf_counter() - t1) / 2 * 1e3
         log(f"host entry point: {host_ms:.2f} ms per call")
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, dem, call)
+    cpu = None if args.no_cpu_baseline else sub_bench("cpu baseline", lambda: cpu_baseline(args.workload, dem, call))
 
     return {
         "metric": "LoS cell-evals/s + total-viewshed cells/s at 2000² DEM; p50/p99 serve latency",
