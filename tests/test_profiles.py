@@ -19,3 +19,17 @@ def test_summaries_name_their_commands():
     for f in files:
         text = open(f).read()
         assert "rocprofv3" in text and "bench.py" in text, f
+
+
+def test_summaries_from_other_sources_are_ignored(tmp_path):
+    """A summary whose recorded source hash, workload or flags differ from the current ones is not read."""
+    for name, reader in (("sweep_tvs2000_traffic.md", bench.read_traffic),
+                         ("tvs2000_counters.md", bench.read_counters)):
+        text = open(os.path.join(bench.ROOT, "profiles", name)).read()
+        assert reader(os.path.join(bench.ROOT, "profiles", name), "tvs2000", 0) is not None
+        digest = bench.kernel_source_digest()
+        other = tmp_path / name
+        other.write_text(text.replace(digest, "0" * len(digest)))
+        assert reader(str(other), "tvs2000", 0) is None
+        assert reader(os.path.join(bench.ROOT, "profiles", name), "tvs8000", 0) is None
+        assert reader(os.path.join(bench.ROOT, "profiles", name), "tvs2000", 64) is None
