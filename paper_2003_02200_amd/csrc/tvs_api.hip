@@ -332,7 +332,7 @@ int sweep_shape(const std::vector<Sector> &S, const std::vector<Chunk> &chunks, 
         float ms = 0.f;
         for (int rep = 0; rep < 2 && rc == TVS_OK; ++rep)  // the first run warms the caches
             if (hipEventRecord(e0, st) != hipSuccess ||
-                launch_sweep(ca, c.maxWx, c.maxRows, dem, demT, skw, V, tab32, tab64, f64, false, rcp, prune, nullptr,
+                launch_sweep(ca, c.maxWx, dem, demT, skw, V, tab32, tab64, f64, false, rcp, prune, nullptr,
                              st, cand) != hipSuccess ||
                 hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
@@ -468,7 +468,7 @@ int run_total(const float *d_dem, int H, int W, double dx, double h0, int n, dou
             HIPCHK(tm.mark());
         }
         HIPCHK(tm.begin(1));
-        HIPCHK(launch_sweep(a, c.maxWx, c.maxRows, d_dem, demT, skw, V, tab32, tab64, f64, scan, rcp, prune, work,
+        HIPCHK(launch_sweep(a, c.maxWx, d_dem, demT, skw, V, tab32, tab64, f64, scan, rcp, prune, work,
                             st, nw));
         HIPCHK(tm.mark());
         if (d_debugV) {

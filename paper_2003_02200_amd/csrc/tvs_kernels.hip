@@ -788,7 +788,8 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
     // 0 .. nseg - 1).
     __shared__ int seg_next;
     if (threadIdx.x == 0) seg_next = NW;
-    if (PRUNE) block_bounds<Tz, SLIDE>(row + TVS_SWEEP_PAD, nb, suf, pre, rmq, slide);  // ends with a barrier
+    // rows of at most 32 samples never reach a bound test (a test needs a finished 32-step block)
+    if (PRUNE && nt > 32) block_bounds<Tz, SLIDE>(row + TVS_SWEEP_PAD, nb, suf, pre, rmq, slide);  // ends with a barrier
     else __syncthreads();
     const int Kc = min(K, nt);  // K may be unbounded
     const int lane = threadIdx.x & 63;
@@ -866,17 +867,30 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowS
 // samples of steps 1 + cM .. (c + 1) M of every POV of the piece (M + 64 NW - 1 samples, a multiple-of-32
 // M, -inf outside the row); every lane carries its horizon, bit mask and ring sums from one window to
 // the next, so each line of sight is walked in order over the whole row, as in the single-window sweep
-// (a 32-step block never straddles two windows; the clipped step K may open the next one). Every target
-// in range is evaluated (no early exit). Samples come from the grid (gathered with the relocation's
-// interpolation) or from skwDEM.
-template <typename Tz, int NW, bool RCP>
+// (a 32-step block never straddles two windows; the clipped step K may open the next one). Samples come
+// from the grid (gathered with the relocation's interpolation) or from skwDEM.
+//
+// With PRUNE the walk has the single-window sweep's block skip and early exit. Before its windows the
+// workgroup takes, over every position its lanes can reach (K either side of the piece), the maximum of
+// each 32-sample block, rounded up to float, and from them the prefix and suffix maxima. A sample's bound
+// comes from the grid values it blends: their maximum plus 2^-40 of their magnitudes, above the double
+// blend's rounding (a few double ulps of those magnitudes), so no sample exceeds its block's entry. A
+// lane's 32 targets of a block lie in two consecutive blocks (the skip test's bound), and every target of
+// the wavefront from step m on lies between the nearest one and the end of the reach (the exit test's).
+// A wavefront whose direction is decided skips its later windows' work, and the workgroup stops loading
+// windows once every wavefront has.
+template <typename Tz, int NW, bool RCP, bool PRUNE>
 __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const RowSrc src,
                                                         const Tz *__restrict__ skw, uint32_t *__restrict__ V,
                                                         const typename Tab<Tz>::type *__restrict__ tab, int M,
-                                                        int pieces, unsigned long long *__restrict__ work) {
+                                                        int pieces, int nbs_cap, unsigned long long *__restrict__ work) {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Tz *win = reinterpret_cast<Tz *>(lds_raw);
+    const int L = M + 64 * NW - 1;
+    float *bm = reinterpret_cast<float *>(win + L);  // PRUNE: block maxima over the reach, then prefix, suffix
+    float *pre = bm + nbs_cap, *suf = pre + nbs_cap;
     __shared__ unsigned long long wg_work;
+    __shared__ int ndone;  // wavefronts that have finished the current direction
     const SecDev &s = a.s[blockIdx.y];
     const int ri = (int)blockIdx.x / pieces, piece = (int)blockIdx.x % pieces;
     if (ri >= s.nrows) return;
@@ -906,17 +920,59 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
         }
         return add_rn((Tz)z, (Tz)0);
     };
-    const int L = M + 64 * NW - 1;
+    // an upper bound of sample p, as a float
+    auto sample_bound = [&](int p) -> float {
+        if (!src.gather) return ru_float(srow[p]);
+        const int j = jlo + p;
+        int d;
+        double r;
+        col_offset(s.T, j, d, r);
+        const int u = t + d;
+        const float *col = F.base + (int64_t)j * F.cs;
+        const float av = col[(int64_t)min(max(u, 0), Hx - 1) * F.rs];
+        if (r != 0.0 && u >= 0 && u < Hx - 1) {
+            const double bv = (double)col[(int64_t)(u + 1) * F.rs];
+            return ru_float(fmax((double)av, bv) + (fabs((double)av) + fabs(bv)) * 0x1p-40);
+        }
+        return av;
+    };
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int q0 = P0 + 64 * wv, q = q0 + lane;
     const bool live = q < nt;
     const int K = s.K;
+    const int last = min(nt - 1, P0 + 64 * NW - 1);  // the piece's last POV
+    const int Kc = min(K, nt);
+    // positions the piece's lanes can reach, and their 32-sample blocks b0 .. b0 + nbs - 1 (nbs <= nbs_cap)
+    const int reach_lo = max(0, P0 - Kc), reach_hi = min(nt - 1, last + Kc);
+    const int b0 = reach_lo >> 5, nbs = (reach_hi >> 5) - b0 + 1;
+    if (PRUNE) {
+        // one block per half wavefront, reduced across its 32 lanes
+        for (int i = (int)threadIdx.x >> 5; i < nbs; i += (int)blockDim.x >> 5) {
+            const int p = ((b0 + i) << 5) + (int)(threadIdx.x & 31);
+            float v = (p >= reach_lo && p <= reach_hi) ? sample_bound(p) : neg_inf<float>();
+            for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 32));
+            if ((threadIdx.x & 31) == 0) bm[i] = v;
+        }
+        __syncthreads();
+        if (wv < 2) {  // prefix maxima by wavefront 0, suffix maxima by wavefront 1
+            float carry = neg_inf<float>();
+            for (int c0 = 0; c0 < nbs; c0 += 64) {
+                const int i = c0 + lane;
+                const int b = wv == 0 ? i : nbs - 1 - i;
+                float x = i < nbs ? bm[b] : neg_inf<float>();
+                x = vmax(wave_prefix_max(x), carry);
+                if (i < nbs) (wv == 0 ? pre : suf)[b] = x;
+                carry = lane63(x);
+            }
+        }
+        __syncthreads();
+    }
+    auto entry = [&](const float *arr, int blk) -> float { return arr[min(max(blk - b0, 0), nbs - 1)]; };
     const Tz h = live ? add_rn(sample(q), h0_of<Tz>(a)) : neg_inf<Tz>();
     uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
     uint32_t e = (K >= 1) ? 0u : 2u;
     unsigned long long evals = 0;
-    const int last = min(nt - 1, P0 + 64 * NW - 1);  // the piece's last POV
 #pragma unroll 1
     for (int DIR = 1; DIR >= -1; DIR -= 2) {
         // steps of this wavefront (its farthest-reaching lane) and of the whole piece (window count)
@@ -925,12 +981,34 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
         const int mbW = DIR > 0 ? min(K, nt - 1 - P0) : min(K, last);
         const int mfull = (mb == K) ? K - 1 : mb;
         const int nwin = mbW >= 1 ? (mbW + M - 1) / M : 0;
-        Tz mx = neg_inf<Tz>();
+        const int own = DIR > 0 ? min(K, nt - 1 - q) : min(K, q);  // this lane's last step
+        // a lane past the row end has a +inf horizon: it never sees a target, never holds back a test
+        Tz mx = live ? neg_inf<Tz>() : -neg_inf<Tz>();
+        // every target of steps m1..m2 of the wavefront with elevation at most zs is hidden
+        auto bounded_by = [&](Tz zs, int m1, int m2) -> bool {
+            const Tz d = sub_rn(zs, h);
+            const Tz b = vmax_plain(slope<RCP>(d, tab[m1 - 1]), slope<RCP>(d, tab[m2 - 1]));
+            return __builtin_amdgcn_ballot_w64(b <= mx) == ~0ull;
+        };
+        auto hidden_from = [&](int mm) -> bool {  // no target of the wavefront from step mm to mb
+            const int bnear = (DIR > 0 ? q0 + mm : top - mm) >> 5;
+            return bounded_by((Tz)entry(DIR > 0 ? suf : pre, bnear), mm, mb);
+        };
+        auto block_hidden = [&](int mm) -> bool {  // no target of steps mm .. mm + 31 on any lane
+            const int first = DIR > 0 ? q + mm : q - mm - 31;
+            return bounded_by((Tz)fmaxf(entry(bm, first >> 5), entry(bm, (first + 31) >> 5)), mm, mm + 31);
+        };
         RingAcc ra;
         uint32_t bits = 0, acc = 0;
-        int m = 1;
+        int m = 1, skipped = 0;
+        bool stop = false, counted = false;
+        if (PRUNE) {
+            __syncthreads();  // the previous direction's count is read by every wavefront
+            if (threadIdx.x == 0) ndone = 0;
+        }
         for (int c = 0; c < nwin; ++c) {
             __syncthreads();  // the previous window is no longer read
+            if (PRUNE && ndone == NW) break;  // every wavefront has finished this direction
             const int origin = DIR > 0 ? P0 + 1 + c * M : P0 - (c + 1) * M;
             for (int x = threadIdx.x; x < L; x += blockDim.x) {
                 const int p = origin + x;
@@ -940,27 +1018,45 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
             const int wend = (c + 1) * M;  // last step held by this window
             // position q + DIR m sits at zb[DIR m]
             const Tz *zb = win + (q - P0) + (DIR > 0 ? -1 - c * M : (c + 1) * M);
-            for (; m + 31 <= min(mfull, wend); m += 32) {
-                const auto *tt = tab + (m - 1);
+            if (!stop) {
+                for (; m + 31 <= min(mfull, wend); m += 32) {
+                    if (PRUNE && m > 1 && block_hidden(m)) {
+                        if (hidden_from(m)) {
+                            stop = true;
+                            break;
+                        }
+                        skipped += max(0, min(own, m + 31) - m + 1);
+                        continue;
+                    }
+                    const auto *tt = tab + (m - 1);
 #pragma unroll
-                for (int k = 0; k < 32; ++k) vis_step(slope<RCP>(sub_rn(zb[DIR * (m + k)], h), tt[k]), mx, bits);
-                if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
+                    for (int k = 0; k < 32; ++k) vis_step(slope<RCP>(sub_rn(zb[DIR * (m + k)], h), tt[k]), mx, bits);
+                    if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
+                }
             }
-            if (m <= mfull && mfull <= wend) {  // the last steps of the wavefront, all in this window
-                for (; m <= mfull; ++m) {
-                    const Tz th = slope<RCP>(sub_rn(zb[DIR * m], h), tab[m - 1]);
-                    acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
-                    mx = vmax_plain(mx, th);
+            if (!stop && m <= mfull && mfull <= wend) {  // the last steps of the wavefront, all in this window
+                if (PRUNE && m > 1) stop = hidden_from(m);
+                if (!stop) {
+                    for (; m <= mfull; ++m) {
+                        const Tz th = slope<RCP>(sub_rn(zb[DIR * m], h), tab[m - 1]);
+                        acc += th > mx ? (uint32_t)(2 * m + 1) : 0u;
+                        mx = vmax_plain(mx, th);
+                    }
                 }
             }
             // the clipped last ring, when this window holds step K
-            if (mb == K && K >= 1 && m == K && K <= wend) {
+            if (!stop && mb == K && K >= 1 && m == K && K <= wend) {
                 e += slope<RCP>(sub_rn(zb[DIR * K], h), tab[K - 1]) > mx ? 1u : 0u;
                 m = K + 1;
             }
+            if (PRUNE && !counted && (stop || (m > mfull && (mb != K || K < 1 || m > K)))) {
+                counted = true;
+                if (lane == 0) atomicAdd(&ndone, 1);
+            }
         }
         U += ra.total() + acc;
-        if (live) evals += (unsigned long long)(DIR > 0 ? min(K, nt - 1 - q) : min(K, q));
+        const int done = stop ? m - 1 : mb;
+        if (live) evals += (unsigned long long)max(0, min(done, own) - skipped);
     }
     if (live) V[skw_row(s, t, a.pitch) + jlo + q] = U | (e << 30);
     if (work) {
@@ -1624,46 +1720,90 @@ bool sweep_row_fits(int maxWx, bool f64) { return sweep_lds_bytes(maxWx, f64) + 
 // LDS (M a multiple of 32, no larger than the longest line of sight of the chunk needs).
 static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int maxWx, int maxRows, int maxK,
                                     const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64,
-                                    bool f64, bool rcp, unsigned long long *work, hipStream_t st) {
+                                    bool f64, bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
     constexpr int NW = 8;
     const size_t elem = f64 ? sizeof(double) : sizeof(float);
     const int steps = std::max(1, std::min(maxK, maxWx));
-    const int mcap = (int)(((size_t)(80 * 1024) / elem - (64 * NW - 1)) / 32) * 32;
+    // the blocks a piece's lanes reach: its 64 NW POVs and K either side, within the row
+    const int nbs_cap = prune ? (std::min(maxWx, 2 * steps + 64 * NW) + 31) / 32 + 2 : 0;
+    // two workgroups per CU: 80 KB each, less the static LDS and the block tables
+    const size_t budget = (size_t)(80 * 1024) - 64 - (size_t)3 * nbs_cap * sizeof(float);
+    const int mcap = (int)((budget / elem - (64 * NW - 1)) / 32) * 32;
     const int M = std::min(mcap, (steps + 31) / 32 * 32);
-    const size_t lds = (size_t)(M + 64 * NW - 1) * elem;
+    const size_t lds = (size_t)(M + 64 * NW - 1) * elem + (size_t)3 * nbs_cap * sizeof(float);
     const int pieces = (maxWx + 64 * NW - 1) / (64 * NW);
     const dim3 grid((unsigned)maxRows * (unsigned)pieces, a.nsec);
-#define TVS_LONG_GO(TZ, RC, TAB)                                                                         \
+#define TVS_LONG_GO(TZ, RC, PR, TAB)                                                                     \
     do {                                                                                                 \
-        auto f = k_sweep_long<TZ, NW, RC>;                                                               \
+        auto f = k_sweep_long<TZ, NW, RC, PR>;                                                           \
         hipError_t e = set_lds(f, lds);                                                                  \
         if (e != hipSuccess) return e;                                                                   \
-        f<<<grid, 64 * NW, lds, st>>>(a, src, (const TZ *)skw, V, TAB, M, pieces, work);                \
+        f<<<grid, 64 * NW, lds, st>>>(a, src, (const TZ *)skw, V, TAB, M, pieces, nbs_cap, work);       \
     } while (0)
     if (f64) {
-        if (rcp) TVS_LONG_GO(double, true, tab64);
-        else TVS_LONG_GO(double, false, tab64);
+        if (prune) {
+            if (rcp) TVS_LONG_GO(double, true, true, tab64);
+            else TVS_LONG_GO(double, false, true, tab64);
+        } else {
+            if (rcp) TVS_LONG_GO(double, true, false, tab64);
+            else TVS_LONG_GO(double, false, false, tab64);
+        }
     } else {
-        if (rcp) TVS_LONG_GO(float, true, tab32);
-        else TVS_LONG_GO(float, false, tab32);
+        if (prune) {
+            if (rcp) TVS_LONG_GO(float, true, true, tab32);
+            else TVS_LONG_GO(float, false, true, tab32);
+        } else {
+            if (rcp) TVS_LONG_GO(float, true, false, tab32);
+            else TVS_LONG_GO(float, false, false, tab32);
+        }
     }
 #undef TVS_LONG_GO
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(const ChunkArgs &a, int maxWx, int maxRows, const float *dem, const float *demT,
+// Longest skewed row of a sector: row t holds the columns whose position lies in (-1, Hx), and the
+// positions of successive columns differ by T (to within the offsets' rounding and snapping, far below
+// a column), so at most (Hx + 1) / T + 1 columns share a row; every column of the frame when T = 0.
+static int sector_row_bound(const SecDev &s, int H, int W) {
+    int Hx, Wx;
+    frame_dims(s.kase, H, W, Hx, Wx);
+    if (!(s.T > 0.0)) return Wx;
+    const double b = floor((double)(Hx + 1) / s.T) + 2.0;
+    return b < (double)Wx ? (int)b : Wx;
+}
+
+hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
                         bool rcp, bool prune, unsigned long long *work, hipStream_t st, int nw) {
     RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
-    if (!sweep_row_fits(maxWx, f64)) {
-        int maxK = 0;
-        for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
-        return launch_sweep_long(a, src, maxWx, maxRows, maxK, skw, V, tab32, tab64, f64, rcp, work, st);
+    // sectors whose rows fit one workgroup's LDS take the single-window sweep, the others the streamed
+    // one (a skinny grid's steep sectors have short rows even when its long side does not fit)
+    ChunkArgs b = a, lng = a;
+    b.nsec = lng.nsec = 0;
+    int fitWx = 0, fitRows = 0, lngWx = 0, lngRows = 0;
+    for (int k = 0; k < a.nsec; ++k) {
+        const int len = std::min(maxWx, sector_row_bound(a.s[k], a.H, a.W));
+        if (sweep_row_fits(len, f64)) {
+            b.s[b.nsec++] = a.s[k];
+            fitWx = std::max(fitWx, len);
+            fitRows = std::max(fitRows, a.s[k].nrows);
+        } else {
+            lng.s[lng.nsec++] = a.s[k];
+            lngWx = std::max(lngWx, len);
+            lngRows = std::max(lngRows, a.s[k].nrows);
+        }
     }
-    const dim3 grid(maxRows, a.nsec);
-    ChunkArgs b = a;
+    if (lng.nsec > 0) {
+        int maxK = 0;
+        for (int k = 0; k < lng.nsec; ++k) maxK = std::max(maxK, std::min(lng.s[k].K, lngWx));
+        const hipError_t e =
+            launch_sweep_long(lng, src, lngWx, lngRows, maxK, skw, V, tab32, tab64, f64, rcp, prune, work, st);
+        if (e != hipSuccess || b.nsec == 0) return e;
+    }
+    maxWx = fitWx;
+    const dim3 grid(fitRows, b.nsec);
     int maxK = 0, slide = 0;
-    for (int k = 0; k < a.nsec; ++k) maxK = std::max(maxK, std::min(a.s[k].K, maxWx));
+    for (int k = 0; k < b.nsec; ++k) maxK = std::max(maxK, std::min(b.s[k].K, maxWx));
     // without the early exit or in the lane-per-target variant no sliding maxima
     const size_t lds = sweep_lds_launch(maxWx, f64, prune && !scan ? maxK : INT_MAX, b.rmq, slide);
     switch (nw == 4 || nw == 8 || nw == 16 ? nw : sweep_waves(lds)) {
