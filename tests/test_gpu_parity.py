@@ -289,6 +289,10 @@ def test_double_rows_beyond_lds_streamed(tvs, orc, H, W, n, R, k):
     np.testing.assert_array_equal(g, gf)
     assert sf.sweep_evals_done == sf.los_evals
     assert 0 < st.sweep_evals_done < st.los_evals
+    # the chunk's long sector streams and its short ones take the single-window sweep, also when both
+    # read skwDEM rows in the compacted layout: the same map
+    gr = tvs.total_viewshed(dem, 10.0, 1.5, n, R, flags=tvs.FLAG_RELOCATE | tvs.FLAG_COMPACT)
+    np.testing.assert_array_equal(g, gr)
     print(f"long rows H={H} W={W} R={R}: {st.sweep_evals_done / st.los_evals:.3f} of the evaluations carried out",
           flush=True)
 
