@@ -25,7 +25,7 @@
  * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE. A skewed row is held in the
  *            LDS of one workgroup when it fits (float rows always; double rows up to about 19,800
  *            samples); longer rows are swept in pieces whose targets stream through LDS windows,
- *            every line of sight walked to its end (no early exit). The lane-per-target sweep
+ *            with the same exact block skip and early exit. The lane-per-target sweep
  *            (TVS_FLAG_SWEEP_SCAN) and batches hold whole rows and return TVS_ERANGE beyond.
  * Results    Areas in square metres, double.
  *
