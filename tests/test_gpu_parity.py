@@ -262,6 +262,9 @@ LONG_DOUBLE = [
     (25000, 2, 4, INF, 2),  # the long rows in the transposed frame (the 90 deg axis)
     (3, 32767, 4, INF, 0),
     (3, 32767, 4, 30000.0, 0),
+    # a skinny grid: only the axis sector along the long side streams; the skewed rows of the others
+    # (22.5 and 45 deg: at most 43 and 19 samples) take the single-window sweep, sized by their bound
+    (16, 32767, 8, 20000.0, 0),
 ]
 
 
