@@ -23,9 +23,10 @@
  *            index distance m < rho = max_dist cos(s') / spacing and its last ring is
  *            clipped at rho.
  * rows, cols 1 .. 32767 each; larger grids return TVS_ERANGE. A skewed row is held in the
- *            LDS of one workgroup when it fits (float rows always; double rows up to about 19,800
- *            samples); longer rows are swept in pieces whose targets stream through LDS windows,
- *            with the same exact block skip and early exit. The lane-per-target sweep
+ *            LDS of one workgroup when it fits (float rows always; double rows up to about 19,000
+ *            samples); longer rows are swept in pieces of POVs, each piece's reach (K samples
+ *            either side) held in LDS, or, for lines of sight too long for that, streamed through
+ *            LDS windows; with the same exact block skip and early exit. The lane-per-target sweep
  *            (TVS_FLAG_SWEEP_SCAN) and batches hold whole rows and return TVS_ERANGE beyond.
  * Results    Areas in square metres, double.
  *

@@ -40,6 +40,8 @@ struct ChunkArgs {
     int32_t k_base; // global index of s[0]
     int32_t pov_i, pov_j;  // singular POV (grid cell)
     int32_t rmq;    // sweep: 1 when the early exit's range-maximum table is in LDS (set by launch_sweep)
+    int32_t pieces; // sweep: > 1 when each row is swept in pieces of piece_povs POVs (set by launch_sweep)
+    int32_t piece_povs;
     int32_t pad1;
 };
 static_assert(sizeof(SecDev) == 56, "sector parameters: 56 bytes");

@@ -691,25 +691,20 @@ __device__ __forceinline__ int row_of_block(int b, int N) {
     return (b & 1) ? c + ((b + 1) >> 1) : c - (b >> 1);
 }
 
-// Skewed row ri of sector s gathered straight from the base frame into LDS (Alg. 6's interpolation:
-// the double blend (1 - r_j) X[u][j] + r_j X[u + 1][j], rows clamped, -0 made +0), with
-// TVS_SWEEP_PAD -inf sentinels on both sides, so that no skwDEM buffer exists in HBM. Consecutive
-// samples read consecutive columns of X: coalesced when the frame's columns are contiguous (the DEM
-// for the 0..45 and 135..180 deg axes, its transpose for the others); neighbouring skewed rows
-// reuse the same cache lines. Returns nt (0 for an empty row).
+// Samples w0 .. w0 + n - 1 of skewed row t (first column jlo) gathered straight from the base frame
+// into row[TVS_SWEEP_PAD ..] (Alg. 6's interpolation: the double blend (1 - r_j) X[u][j] + r_j X[u + 1][j],
+// rows clamped, -0 made +0), with TVS_SWEEP_PAD -inf sentinels on both sides, so that no skwDEM buffer
+// exists in HBM. Consecutive samples read consecutive columns of X: coalesced when the frame's columns
+// are contiguous (the DEM for the 0..45 and 135..180 deg axes, its transpose for the others);
+// neighbouring skewed rows reuse the same cache lines.
 template <typename Tz>
-__device__ __forceinline__ int gather_row(const FrameRef &F, int Hx, int Wx, const SecDev &s, int ri, Tz *row,
-                                          int &jlo) {
-    const int t = s.t0 + ri;
-    jlo = row_first(s.T, t, Hx, Wx);
-    const int jhi = row_last(s.T, t, Hx, Wx);
-    const int nt = jhi - jlo + 1;
-    if (nt <= 0) return 0;
-    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
+__device__ __forceinline__ void gather_span(const FrameRef &F, int Hx, const SecDev &s, int t, int jlo, int w0, int n,
+                                            Tz *row) {
+    for (int x = threadIdx.x; x < n + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
         const int q = x - TVS_SWEEP_PAD;
         Tz v = neg_inf<Tz>();
-        if (q >= 0 && q < nt) {
-            const int j = jlo + q;
+        if (q >= 0 && q < n) {
+            const int j = jlo + w0 + q;
             int d;
             double r;
             col_offset(s.T, j, d, r);
@@ -726,6 +721,18 @@ __device__ __forceinline__ int gather_row(const FrameRef &F, int Hx, int Wx, con
         row[x] = v;
     }
     __syncthreads();
+}
+
+// Skewed row ri of sector s, all of it. Returns nt (0 for an empty row).
+template <typename Tz>
+__device__ __forceinline__ int gather_row(const FrameRef &F, int Hx, int Wx, const SecDev &s, int ri, Tz *row,
+                                          int &jlo) {
+    const int t = s.t0 + ri;
+    jlo = row_first(s.T, t, Hx, Wx);
+    const int jhi = row_last(s.T, t, Hx, Wx);
+    const int nt = jhi - jlo + 1;
+    if (nt <= 0) return 0;
+    gather_span<Tz>(F, Hx, s, t, jlo, 0, nt, row);
     return nt;
 }
 
@@ -738,37 +745,66 @@ struct RowSrc {
     int pad;
 };
 
-// Skewed row `ri` (existing samples jlo..jlo+nt-1) into LDS with TVS_SWEEP_PAD -inf sentinels on both
-// sides, from the grid or from skwDEM. Returns nt (0 for an empty row).
+// Skewed row `ri` (existing samples jlo .. jlo + nt - 1) into LDS with TVS_SWEEP_PAD -inf sentinels on
+// both sides, from the grid or from skwDEM: all of it (pieces <= 1), or the reach of piece `piece` of
+// `povs` POVs: its POVs P0 .. p1 - 1 and min(K, nt) samples either side, within the row. Every target of
+// those POVs is loaded, and a POV's steps to the loaded span's ends are those to the row's ends, or more
+// than K. Returns the samples loaded (0 for an empty row or piece): samples w0 .. w0 + n - 1, of which
+// p_lo .. p_hi - 1 (counted from w0) are the POVs to sweep.
+template <typename Tz>
+__device__ __forceinline__ int load_piece(const ChunkArgs &a, const RowSrc &src, const SecDev &s, int ri, int piece,
+                                          int pieces, int povs, const Tz *skw, Tz *row, int &jlo, int &w0, int &p_lo,
+                                          int &p_hi) {
+    int Hx, Wx;
+    frame_dims(s.kase, a.H, a.W, Hx, Wx);
+    const int t = s.t0 + ri;
+    jlo = row_first(s.T, t, Hx, Wx);
+    const int nt = row_last(s.T, t, Hx, Wx) - jlo + 1;
+    if (nt <= 0) return 0;
+    int n = nt;
+    w0 = 0;
+    p_lo = 0;
+    p_hi = nt;
+    if (pieces > 1) {
+        const int P0 = piece * povs;
+        if (P0 >= nt) return 0;
+        const int Kc = min(s.K, nt), p1 = min(nt, P0 + povs);
+        w0 = max(0, P0 - Kc);
+        n = min(nt - 1, p1 - 1 + Kc) - w0 + 1;
+        p_lo = P0 - w0;
+        p_hi = p1 - w0;
+    }
+    if (src.gather) {
+        gather_span<Tz>(frame_ref(s.kase, a.H, a.W, src.dem, src.demT), Hx, s, t, jlo, w0, n, row);
+        return n;
+    }
+    const Tz *src_row = skw + skw_row(s, t, a.pitch) + jlo + w0;
+    for (int x = threadIdx.x; x < n + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
+        const int q = x - TVS_SWEEP_PAD;
+        row[x] = (q >= 0 && q < n) ? src_row[q] : neg_inf<Tz>();
+    }
+    __syncthreads();
+    return n;
+}
+
+// The whole of skewed row `ri`. Returns nt (0 for an empty row).
 template <typename Tz>
 __device__ __forceinline__ int load_row(const ChunkArgs &a, const RowSrc &src, const SecDev &s, int ri,
                                         const Tz *skw, Tz *row, int &jlo) {
-    int Hx, Wx;
-    frame_dims(s.kase, a.H, a.W, Hx, Wx);
-    if (src.gather) return gather_row<Tz>(frame_ref(s.kase, a.H, a.W, src.dem, src.demT), Hx, Wx, s, ri, row, jlo);
-    const int t = s.t0 + ri;
-    jlo = row_first(s.T, t, Hx, Wx);
-    const int jhi = row_last(s.T, t, Hx, Wx);
-    const int nt = jhi - jlo + 1;
-    if (nt <= 0) return 0;
-    const Tz *src_row = skw + skw_row(s, t, a.pitch) + jlo;
-    for (int x = threadIdx.x; x < nt + 2 * TVS_SWEEP_PAD; x += blockDim.x) {
-        const int q = x - TVS_SWEEP_PAD;
-        row[x] = (q >= 0 && q < nt) ? src_row[q] : neg_inf<Tz>();
-    }
-    __syncthreads();
-    return nt;
+    int w0, p_lo, p_hi;
+    return load_piece<Tz>(a, src, s, ri, 0, 1, 0, skw, row, jlo, w0, p_lo, p_hi);
 }
 
 // Sweeps a skewed row of nt samples held in LDS (row[TVS_SWEEP_PAD + q], -inf sentinels on both
 // sides, room for the early exit's block maxima after them) and stores U | e << 30 of POV q at
-// dst[q]. Returns the evaluations this lane carried out when COUNT is set. After the row lie
+// dst[q], for the POVs p_lo <= q < p_hi (every sample is a target). Returns the evaluations this
+// lane carried out when COUNT is set. After the row lie
 // the suffix and prefix block maxima, then (use_rmq) the range-maximum table; with SLIDE the
 // table of SLIDE levels, then the sliding maxima of 40 samples at every 8th position.
 template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE, bool COUNT>
 __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
                                               const typename Tab<Tz>::type *__restrict__ tab,
-                                              uint32_t *__restrict__ dst, bool use_rmq) {
+                                              uint32_t *__restrict__ dst, bool use_rmq, int p_lo, int p_hi) {
     const int nb = (nt + 31) >> 5;
     Tz *suf = nullptr, *pre = nullptr;
     float *rmq, *slide = nullptr;
@@ -794,18 +830,18 @@ __device__ __forceinline__ uint32_t sweep_row(Tz *row, int nt, int K, Tz h0,
     const int Kc = min(K, nt);  // K may be unbounded
     const int lane = threadIdx.x & 63;
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int nseg = (nt + 63) >> 6;
+    const int nseg = (p_hi - p_lo + 63) >> 6;
     uint32_t evals = 0;
     for (int k = wv; k < nseg;) {
         const int c = (nseg - 1) >> 1, sg = (k & 1) ? c + ((k + 1) >> 1) : c - (k >> 1);  // middle-out
-        const int q0 = sg << 6;
+        const int q0 = p_lo + (sg << 6);
         const int q = q0 + lane;
-        const bool live = q < nt;
+        const bool live = q < p_hi;
         const Tz *zp = row + TVS_SWEEP_PAD + q;
         const Tz h = add_rn(zp[0], h0);
         uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
         uint32_t e = (K >= 1) ? 0u : 2u;
-        const int top = min(nt - 1, q0 + 63);
+        const int top = min(p_hi - 1, q0 + 63);
         const int fwd = min(K, nt - 1 - q0);
         const int bwd = min(K, top);
         int df, db;
@@ -836,6 +872,8 @@ __device__ __forceinline__ void add_work(unsigned long long *work, unsigned long
     if (threadIdx.x == 0) atomicAdd(&work[slot & 63], wg_work);
 }
 
+// One skewed row per workgroup (a.pieces <= 1), or one piece of a row too long for the LDS: the reach
+// of a.piece_povs consecutive POVs, swept as a row of its own.
 template <typename Tz, int NW, bool RCP, bool PRUNE, int SLIDE = 0>
 __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowSrc src, const Tz *__restrict__ skw,
                                                    uint32_t *__restrict__ V,
@@ -845,24 +883,31 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowS
     Tz *row = reinterpret_cast<Tz *>(lds_raw);
     __shared__ unsigned long long wg_work;
     const SecDev &s = a.s[blockIdx.y];
-    if ((int)blockIdx.x >= s.nrows) return;
-    const int ri = row_of_block(blockIdx.x, s.nrows);
-    int jlo;
-    const int nt = load_row<Tz>(a, src, s, ri, skw, row, jlo);
-    if (nt == 0) return;
-    uint32_t *dst = V + skw_row(s, s.t0 + ri, a.pitch) + jlo;
+    // with pieces, workgroup x sweeps piece x mod pieces of row x / pieces
+    const int pieces = a.pieces;
+    const int rb = pieces > 1 ? (int)blockIdx.x / pieces : (int)blockIdx.x;
+    if (rb >= s.nrows) return;
+    const int ri = row_of_block(rb, s.nrows);
+    int jlo, w0, p_lo, p_hi;
+    const int n = load_piece<Tz>(a, src, s, ri, (int)blockIdx.x - rb * pieces, pieces, a.piece_povs, skw, row, jlo,
+                                 w0, p_lo, p_hi);
+    if (n == 0) return;
+    uint32_t *dst = V + skw_row(s, s.t0 + ri, a.pitch) + jlo + w0;
     if (!work) {
-        sweep_row<Tz, NW, RCP, PRUNE, SLIDE, false>(row, nt, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0);
+        sweep_row<Tz, NW, RCP, PRUNE, SLIDE, false>(row, n, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0, p_lo, p_hi);
         return;
     }
     if (threadIdx.x == 0) wg_work = 0;
-    const uint32_t evals = sweep_row<Tz, NW, RCP, PRUNE, SLIDE, true>(row, nt, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0);
+    const uint32_t evals =
+        sweep_row<Tz, NW, RCP, PRUNE, SLIDE, true>(row, n, s.K, h0_of<Tz>(a), tab, dst, a.rmq != 0, p_lo, p_hi);
     add_work(work, wg_work, evals, blockIdx.x + 7 * blockIdx.y);
 }
 
 // ---------------------------------------------------------- rows longer than the LDS holds
-// A skewed row too long for one workgroup's LDS (double rows beyond about 19,800 samples) is swept
-// in pieces: workgroup (row, piece) owns the piece's 64 NW consecutive POVs, one 64-POV segment per
+// A skewed row too long for one workgroup's LDS (double rows beyond about 19,000 samples) whose lines of
+// sight are too long for k_sweep's pieces (a piece's reach, its POVs and K samples either side, must fit
+// the LDS with the range table) is swept here, also in pieces: workgroup (row, piece) owns the piece's
+// 64 NW consecutive POVs, one 64-POV segment per
 // wavefront, and streams the targets of both directions through an LDS window. Window c holds the
 // samples of steps 1 + cM .. (c + 1) M of every POV of the piece (M + 64 NW - 1 samples, a multiple-of-32
 // M, -inf outside the row); every lane carries its horizon, bit mask and ring sums from one window to
@@ -872,13 +917,23 @@ __global__ __launch_bounds__(64 * NW) void k_sweep(const ChunkArgs a, const RowS
 //
 // With PRUNE the walk has the single-window sweep's block skip and early exit. Before its windows the
 // workgroup takes, over every position its lanes can reach (K either side of the piece), the maximum of
-// each 32-sample block, rounded up to float, and from them the prefix and suffix maxima. A sample's bound
-// comes from the grid values it blends: their maximum plus 2^-40 of their magnitudes, above the double
-// blend's rounding (a few double ulps of those magnitudes), so no sample exceeds its block's entry. A
-// lane's 32 targets of a block lie in two consecutive blocks (the skip test's bound), and every target of
-// the wavefront from step m on lies between the nearest one and the end of the reach (the exit test's).
-// A wavefront whose direction is decided skips its later windows' work, and the workgroup stops loading
-// windows once every wavefront has.
+// each 32-sample block, rounded up to float, and from them the prefix and suffix maxima and the maxima of
+// adjacent pairs. A sample's bound comes from the grid values it blends: their maximum plus 2^-40 of their
+// magnitudes, above the double blend's rounding (a few double ulps of those magnitudes), so no sample
+// exceeds its block's entry. A lane's 32 targets of a block lie in two consecutive blocks (the skip
+// test's bound, one pair entry), and every target of the wavefront from step m on lies between the
+// nearest one and the end of the reach (the exit test's). As in the single-window sweep, a block after
+// one in which at least 32 lanes saw a target is not tested. A wavefront whose direction is decided
+// skips its later windows' work, and the workgroup stops loading windows once every wavefront has.
+
+// Entries of the long-row sweep's pair maxima beyond each end of a piece's reach: a lane's pair entry
+// lies at most 4 blocks past the reach (its last steps' targets beyond the row end) or 3 before it.
+constexpr int LONG_PAD = 8;
+
+template <int D> struct DirTag {
+    static constexpr int value = D;
+};
+
 template <typename Tz, int NW, bool RCP, bool PRUNE>
 __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const RowSrc src,
                                                         const Tz *__restrict__ skw, uint32_t *__restrict__ V,
@@ -887,8 +942,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
     extern __shared__ __align__(16) unsigned char lds_raw[];
     Tz *win = reinterpret_cast<Tz *>(lds_raw);
     const int L = M + 64 * NW - 1;
-    float *bm = reinterpret_cast<float *>(win + L);  // PRUNE: block maxima over the reach, then prefix, suffix
-    float *pre = bm + nbs_cap, *suf = pre + nbs_cap;
+    // PRUNE: the block maxima's prefix and suffix maxima, then the maxima of adjacent pairs (with
+    // LONG_PAD entries either side)
+    float *pre = reinterpret_cast<float *>(win + L), *suf = pre + nbs_cap, *pm = suf + nbs_cap + LONG_PAD;
     __shared__ unsigned long long wg_work;
     __shared__ int ndone;  // wavefronts that have finished the current direction
     const SecDev &s = a.s[blockIdx.y];
@@ -952,17 +1008,26 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
             const int p = ((b0 + i) << 5) + (int)(threadIdx.x & 31);
             float v = (p >= reach_lo && p <= reach_hi) ? sample_bound(p) : neg_inf<float>();
             for (int o = 16; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 32));
-            if ((threadIdx.x & 31) == 0) bm[i] = v;
+            if ((threadIdx.x & 31) == 0) pre[i] = suf[i] = v;
         }
         __syncthreads();
-        if (wv < 2) {  // prefix maxima by wavefront 0, suffix maxima by wavefront 1
+        // entry i covers blocks b0 + i and b0 + i + 1; blocks outside the reach hold no target a lane
+        // evaluates (positions past the row or beyond K of every lane): -inf
+        for (int i = (int)threadIdx.x - LONG_PAD; i < nbs + LONG_PAD; i += (int)blockDim.x) {
+            const float x = (i >= 0 && i < nbs) ? pre[i] : neg_inf<float>();
+            const float y = (i + 1 >= 0 && i + 1 < nbs) ? pre[i + 1] : neg_inf<float>();
+            pm[i] = fmaxf(x, y);
+        }
+        __syncthreads();
+        if (wv < 2) {  // prefix maxima by wavefront 0, suffix maxima by wavefront 1, in place
+            float *arr = wv == 0 ? pre : suf;
             float carry = neg_inf<float>();
             for (int c0 = 0; c0 < nbs; c0 += 64) {
                 const int i = c0 + lane;
                 const int b = wv == 0 ? i : nbs - 1 - i;
-                float x = i < nbs ? bm[b] : neg_inf<float>();
+                float x = i < nbs ? arr[b] : neg_inf<float>();
                 x = vmax(wave_prefix_max(x), carry);
-                if (i < nbs) (wv == 0 ? pre : suf)[b] = x;
+                if (i < nbs) arr[b] = x;
                 carry = lane63(x);
             }
         }
@@ -973,8 +1038,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
     uint32_t U = (K >= 1) ? 2u : 0u;  // the POV's own ring, once per direction
     uint32_t e = (K >= 1) ? 0u : 2u;
     unsigned long long evals = 0;
-#pragma unroll 1
-    for (int DIR = 1; DIR >= -1; DIR -= 2) {
+    // one direction; a compile-time DIR folds each step's window offset into the LDS reads
+    auto walk = [&](auto dir) {
+        constexpr int DIR = decltype(dir)::value;
         // steps of this wavefront (its farthest-reaching lane) and of the whole piece (window count)
         const int top = min(nt - 1, q0 + 63);
         const int mb = q0 >= nt ? 0 : DIR > 0 ? min(K, nt - 1 - q0) : min(K, top);
@@ -994,13 +1060,17 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
             const int bnear = (DIR > 0 ? q0 + mm : top - mm) >> 5;
             return bounded_by((Tz)entry(DIR > 0 ? suf : pre, bnear), mm, mb);
         };
-        auto block_hidden = [&](int mm) -> bool {  // no target of steps mm .. mm + 31 on any lane
-            const int first = DIR > 0 ? q + mm : q - mm - 31;
-            return bounded_by((Tz)fmaxf(entry(bm, first >> 5), entry(bm, (first + 31) >> 5)), mm, mm + 31);
+        // no target of steps mm .. mm + 31 on any lane: the lane's targets from position `first` on lie
+        // in blocks first >> 5 and the next; for mm = 1 + 32 k that pair's entry is k after (DIR > 0) or
+        // before (DIR < 0) the one for mm = 1, and stays within LONG_PAD of the reach's entries
+        const float *pl = pm + (((DIR > 0 ? q + 1 : q - 32) >> 5) - b0);
+        auto block_hidden = [&](int mm) -> bool {
+            return bounded_by((Tz)pl[DIR * ((mm - 1) >> 5)], mm, mm + 31);
         };
         RingAcc ra;
         uint32_t bits = 0, acc = 0;
         int m = 1, skipped = 0;
+        int busy = 0;  // lanes that saw a target in the last block: from 32 on, the next is not tested
         bool stop = false, counted = false;
         if (PRUNE) {
             __syncthreads();  // the previous direction's count is read by every wavefront
@@ -1020,7 +1090,8 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
             const Tz *zb = win + (q - P0) + (DIR > 0 ? -1 - c * M : (c + 1) * M);
             if (!stop) {
                 for (; m + 31 <= min(mfull, wend); m += 32) {
-                    if (PRUNE && m > 1 && block_hidden(m)) {
+                    if (PRUNE) m = __builtin_amdgcn_readfirstlane(m);  // keeps the table loads scalar
+                    if (PRUNE && m > 1 && busy < 32 && block_hidden(m)) {
                         if (hidden_from(m)) {
                             stop = true;
                             break;
@@ -1031,7 +1102,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
                     const auto *tt = tab + (m - 1);
 #pragma unroll
                     for (int k = 0; k < 32; ++k) vis_step(slope<RCP>(sub_rn(zb[DIR * (m + k)], h), tt[k]), mx, bits);
-                    if (__builtin_amdgcn_ballot_w64(bits != 0u)) ra.add(bits, m);
+                    const unsigned long long seen = __builtin_amdgcn_ballot_w64(bits != 0u);
+                    if (seen) ra.add(bits, m);
+                    if (PRUNE) busy = __builtin_amdgcn_readfirstlane((int)__popcll(seen));
                 }
             }
             if (!stop && m <= mfull && mfull <= wend) {  // the last steps of the wavefront, all in this window
@@ -1057,7 +1130,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_long(const ChunkArgs a, const
         U += ra.total() + acc;
         const int done = stop ? m - 1 : mb;
         if (live) evals += (unsigned long long)max(0, min(done, own) - skipped);
-    }
+    };
+    walk(DirTag<1>());
+    walk(DirTag<-1>());
     if (live) V[skw_row(s, t, a.pitch) + jlo + q] = U | (e << 30);
     if (work) {
         if (threadIdx.x == 0) wg_work = 0;
@@ -1108,8 +1183,9 @@ __global__ __launch_bounds__(64 * NW) void k_sweep_batch(const BatchEnt *__restr
         frame_dims(E.s.kase, E.H, E.W, Hx, Wx);
         const int nt = gather_row<Tz>(frame_ref(E.s.kase, E.H, E.W, E.dem, E.demT), Hx, Wx, E.s, ri, row, jlo);
         uint32_t *dst = V + skw_row(E.s, E.s.t0 + ri, E.pitch) + jlo;
-        if (nt > 0 && !work) sweep_row<Tz, NW, RCP, true, SLIDE, false>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0);
-        if (nt > 0 && work) evals += sweep_row<Tz, NW, RCP, true, SLIDE, true>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0);
+        if (nt > 0 && !work) sweep_row<Tz, NW, RCP, true, SLIDE, false>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0, 0, nt);
+        if (nt > 0 && work) evals += sweep_row<Tz, NW, RCP, true, SLIDE, true>(row, nt, E.s.K, h0_of<Tz>(E), tab, dst, rmq != 0, 0,
+                                                                          nt);
         __syncthreads();  // the row is read by every wavefront before the next gather
     }
     if (work) add_work(work, wg_work, evals, blockIdx.x);
@@ -1726,11 +1802,13 @@ static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int m
     const int steps = std::max(1, std::min(maxK, maxWx));
     // the blocks a piece's lanes reach: its 64 NW POVs and K either side, within the row
     const int nbs_cap = prune ? (std::min(maxWx, 2 * steps + 64 * NW) + 31) / 32 + 2 : 0;
+    // prefix, suffix and padded pair maxima of the blocks
+    const size_t tables = prune ? ((size_t)3 * nbs_cap + 2 * LONG_PAD) * sizeof(float) : 0;
     // two workgroups per CU: 80 KB each, less the static LDS and the block tables
-    const size_t budget = (size_t)(80 * 1024) - 64 - (size_t)3 * nbs_cap * sizeof(float);
+    const size_t budget = (size_t)(80 * 1024) - 64 - tables;
     const int mcap = (int)((budget / elem - (64 * NW - 1)) / 32) * 32;
     const int M = std::min(mcap, (steps + 31) / 32 * 32);
-    const size_t lds = (size_t)(M + 64 * NW - 1) * elem + (size_t)3 * nbs_cap * sizeof(float);
+    const size_t lds = (size_t)(M + 64 * NW - 1) * elem + tables;
     const int pieces = (maxWx + 64 * NW - 1) / (64 * NW);
     const dim3 grid((unsigned)maxRows * (unsigned)pieces, a.nsec);
 #define TVS_LONG_GO(TZ, RC, PR, TAB)                                                                     \
@@ -1772,18 +1850,42 @@ static int sector_row_bound(const SecDev &s, int H, int W) {
     return b < (double)Wx ? (int)b : Wx;
 }
 
+// Does a row of len samples fit one workgroup's LDS with the early exit's range table?
+static bool row_table_fits(int len, bool f64) {
+    const size_t nbx = ((size_t)len + 31) / 32;
+    return sweep_lds_bytes(len, f64) + (size_t)RMQ_LEVELS * nbx * sizeof(float) + 64 <= (size_t)lds_cap();
+}
+
+// POVs per piece for rows swept in pieces with lines of sight of at most kc steps: a multiple of 64, at
+// least 2048 and 2 kc (a piece loads (P + 2 kc) / P samples per POV), as long as the reach fits the LDS
+// with the range table; 0 when fewer than 512 would.
+static int piece_povs(int kc, bool f64) {
+    int P = (std::max(2048, 2 * kc) + 63) / 64 * 64;
+    while (P >= 512 && !row_table_fits(P + 2 * kc, f64)) P -= 64;
+    return P >= 512 ? P : 0;
+}
+
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
                         bool rcp, bool prune, unsigned long long *work, hipStream_t st, int nw) {
     RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
-    // sectors whose rows fit one workgroup's LDS take the single-window sweep, the others the streamed
-    // one (a skinny grid's steep sectors have short rows even when its long side does not fit)
-    ChunkArgs b = a, lng = a;
-    b.nsec = lng.nsec = 0;
-    int fitWx = 0, fitRows = 0, lngWx = 0, lngRows = 0;
+    // Sectors whose rows fit one workgroup's LDS with the early exit's range table take the
+    // single-window sweep whole; with the bounds on, longer rows whose lines of sight are short enough
+    // take it in pieces, each piece's reach in LDS with its own tables; the rest take it whole if their
+    // rows fit without the table, else stream through windows. Each group is a launch of its own (a
+    // skinny grid's steep sectors have short rows even when its long side does not fit).
+    ChunkArgs b = a, pc = a, lng = a;
+    b.nsec = pc.nsec = lng.nsec = 0;
+    int fitWx = 0, fitRows = 0, pcWx = 0, pcRows = 0, pcK = 0, lngWx = 0, lngRows = 0;
     for (int k = 0; k < a.nsec; ++k) {
         const int len = std::min(maxWx, sector_row_bound(a.s[k], a.H, a.W));
-        if (sweep_row_fits(len, f64)) {
+        const int kc = std::min(a.s[k].K, len);
+        if (!scan && prune && !row_table_fits(len, f64) && piece_povs(kc, f64) > 0) {
+            pc.s[pc.nsec++] = a.s[k];
+            pcWx = std::max(pcWx, len);
+            pcRows = std::max(pcRows, a.s[k].nrows);
+            pcK = std::max(pcK, kc);
+        } else if (sweep_row_fits(len, f64)) {
             b.s[b.nsec++] = a.s[k];
             fitWx = std::max(fitWx, len);
             fitRows = std::max(fitRows, a.s[k].nrows);
@@ -1798,8 +1900,25 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const f
         for (int k = 0; k < lng.nsec; ++k) maxK = std::max(maxK, std::min(lng.s[k].K, lngWx));
         const hipError_t e =
             launch_sweep_long(lng, src, lngWx, lngRows, maxK, skw, V, tab32, tab64, f64, rcp, prune, work, st);
-        if (e != hipSuccess || b.nsec == 0) return e;
+        if (e != hipSuccess) return e;
     }
+    if (pc.nsec > 0) {
+        // every piece's reach is at most P + 2 pcK samples
+        const int P = piece_povs(pcK, f64);
+        pc.pieces = (pcWx + P - 1) / P;
+        pc.piece_povs = P;
+        int slide = 0;
+        const size_t lds = sweep_lds_launch(std::min(pcWx, P + 2 * pcK), f64, pcK, pc.rmq, slide);
+        const dim3 grid((unsigned)pcRows * (unsigned)pc.pieces, pc.nsec);
+        hipError_t e;
+        switch (sweep_waves(lds)) {
+        case 4: e = sweep_nw<4>(pc, src, grid, lds, skw, V, tab32, tab64, f64, false, rcp, true, slide, work, st); break;
+        case 8: e = sweep_nw<8>(pc, src, grid, lds, skw, V, tab32, tab64, f64, false, rcp, true, slide, work, st); break;
+        default: e = sweep_nw<16>(pc, src, grid, lds, skw, V, tab32, tab64, f64, false, rcp, true, slide, work, st);
+        }
+        if (e != hipSuccess) return e;
+    }
+    if (b.nsec == 0) return hipSuccess;
     maxWx = fitWx;
     const dim3 grid(fitRows, b.nsec);
     int maxK = 0, slide = 0;
