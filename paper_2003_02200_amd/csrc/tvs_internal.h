@@ -93,8 +93,9 @@ hipError_t launch_relocate(const ChunkArgs &a, int maxWx, int maxRows, const flo
 // transposed grid, serves the 45..135 deg axes; null reads the grid down its columns); otherwise it
 // reads the row from the skwDEM buffer the relocation wrote.
 // nw: waves per workgroup of the lane-per-POV sweep (4, 8 or 16; otherwise chosen from the LDS the
-// row takes); the sectors whose rows are longer than the LDS holds take the streamed sweep, in a
-// launch of their own, whatever nw says. maxWx bounds every row's length (the frames' widths).
+// row takes); the sectors whose rows are longer than the LDS holds take the sweep in pieces or the
+// streamed sweep, in launches of their own, whatever nw says. maxWx bounds every row's length (the
+// frames' widths).
 hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const float *demT,
                         const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64, bool f64, bool scan,
                         bool rcp, bool prune, unsigned long long *work, hipStream_t st, int nw = 0);

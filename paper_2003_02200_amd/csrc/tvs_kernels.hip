@@ -1792,8 +1792,9 @@ int sweep_waves(size_t lds) {
 
 bool sweep_row_fits(int maxWx, bool f64) { return sweep_lds_bytes(maxWx, f64) + 64 <= (size_t)lds_cap(); }
 
-// Rows that do not fit the LDS: pieces of 512 POVs (8 waves), windows of M steps in about 80 KB of
-// LDS (M a multiple of 32, no larger than the longest line of sight of the chunk needs).
+// Rows that do not fit the LDS, with lines of sight too long for k_sweep's pieces: pieces of 512 POVs
+// (8 waves), windows of M steps in about 80 KB of LDS (M a multiple of 32, no larger than the longest
+// line of sight of the chunk needs).
 static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int maxWx, int maxRows, int maxK,
                                     const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64,
                                     bool f64, bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
