@@ -1793,8 +1793,8 @@ int sweep_waves(size_t lds) {
 bool sweep_row_fits(int maxWx, bool f64) { return sweep_lds_bytes(maxWx, f64) + 64 <= (size_t)lds_cap(); }
 
 // Rows that do not fit the LDS, with lines of sight too long for k_sweep's pieces: pieces of 512 POVs
-// (8 waves), windows of M steps in about 80 KB of LDS (M a multiple of 32, no larger than the longest
-// line of sight of the chunk needs).
+// (8 waves), windows of M steps in about 40 KB of LDS with the block tables (M a multiple of 32, no
+// larger than the longest line of sight of the chunk needs).
 static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int maxWx, int maxRows, int maxK,
                                     const void *skw, uint32_t *V, const float2 *tab32, const double2 *tab64,
                                     bool f64, bool rcp, bool prune, unsigned long long *work, hipStream_t st) {
@@ -1805,10 +1805,12 @@ static hipError_t launch_sweep_long(const ChunkArgs &a, const RowSrc &src, int m
     const int nbs_cap = prune ? (std::min(maxWx, 2 * steps + 64 * NW) + 31) / 32 + 2 : 0;
     // prefix, suffix and padded pair maxima of the blocks
     const size_t tables = prune ? ((size_t)3 * nbs_cap + 2 * LONG_PAD) * sizeof(float) : 0;
-    // two workgroups per CU: 80 KB each, less the static LDS and the block tables
-    const size_t budget = (size_t)(80 * 1024) - 64 - tables;
-    const int mcap = (int)((budget / elem - (64 * NW - 1)) / 32) * 32;
+    // four workgroups per CU (32 waves): 40 KB each, less the static LDS and the block tables (at most
+    // 12.4 KB, at 32,767 samples); twice that, two per CU, ran 20 % slower
+    const size_t budget = (size_t)(40 * 1024) - 64 - tables;
+    const int mcap = (int)(((long long)(budget / elem) - (64 * NW - 1)) / 32) * 32;
     const int M = std::min(mcap, (steps + 31) / 32 * 32);
+    if (M < 32) return hipErrorInvalidValue;  // unreachable for sides up to 32,767
     const size_t lds = (size_t)(M + 64 * NW - 1) * elem + tables;
     const int pieces = (maxWx + 64 * NW - 1) / (64 * NW);
     const dim3 grid((unsigned)maxRows * (unsigned)pieces, a.nsec);
