@@ -1874,9 +1874,11 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const f
     RowSrc src{dem, demT, skw == nullptr ? 1 : 0, 0};
     // Sectors whose rows fit one workgroup's LDS with the early exit's range table take the
     // single-window sweep whole; with the bounds on, longer rows whose lines of sight are short enough
-    // take it in pieces, each piece's reach in LDS with its own tables; the rest take it whole if their
-    // rows fit without the table, else stream through windows. Each group is a launch of its own (a
-    // skinny grid's steep sectors have short rows even when its long side does not fit).
+    // take it in pieces, each piece's reach in LDS with its own tables, and the rest stream through
+    // windows (with their block tables: faster than a whole row without the range table); without the
+    // bounds (or in the lane-per-target variant) rows that fit the LDS take it whole. Each group is a
+    // launch of its own (a skinny grid's steep sectors have short rows even when its long side does
+    // not fit).
     ChunkArgs b = a, pc = a, lng = a;
     b.nsec = pc.nsec = lng.nsec = 0;
     int fitWx = 0, fitRows = 0, pcWx = 0, pcRows = 0, pcK = 0, lngWx = 0, lngRows = 0;
@@ -1888,7 +1890,7 @@ hipError_t launch_sweep(const ChunkArgs &a, int maxWx, const float *dem, const f
             pcWx = std::max(pcWx, len);
             pcRows = std::max(pcRows, a.s[k].nrows);
             pcK = std::max(pcK, kc);
-        } else if (sweep_row_fits(len, f64)) {
+        } else if (sweep_row_fits(len, f64) && (scan || !prune || row_table_fits(len, f64))) {
             b.s[b.nsec++] = a.s[k];
             fitWx = std::max(fitWx, len);
             fitRows = std::max(fitRows, a.s[k].nrows);

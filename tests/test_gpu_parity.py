@@ -228,15 +228,16 @@ def test_early_exit_equals_full_walk(tvs, orc, H, W, n, R, kind):
 # Rows long enough to take the sweep's other bound paths: an unbounded distance on 4000-sample rows
 # (ranges beyond the range table's 64 blocks fall back to the row-end maxima), and rows of 18000
 # doubles or 32767 floats, whose LDS leaves no room for the range table: with bounded lines of sight
-# they are swept in pieces (each piece's reach with its own tables), unbounded ones whole (early exit
-# on the row-end maxima alone, no block skipping). Two sectors keep the skewed arrays small (tan s' = 0).
+# they are swept in pieces (each piece's reach with its own tables), unbounded ones stream through LDS
+# windows (and, without the bounds, are swept whole). Two sectors keep the skewed arrays small
+# (tan s' = 0).
 # unbounded steps (the block-pair skip test, exit ranges past the table: the accumulated maxima);
 # 1900 steps (the most the sliding maxima take with the 6-level table: exit ranges up to 61 blocks);
 # 1950 and 3800 steps (the 7-level table: exit ranges up to 63 and 122 blocks); rows beyond the
-# table's LDS in pieces and whole; float rows with the 7-level table, and beyond the table's LDS
+# table's LDS in pieces and streamed; float rows with the 7-level table, and beyond the table's LDS
 LONG_ROWS = [(5, 4000, INF, 0, P_DEFAULT), (5, 4000, 19000.0, 0, P_DEFAULT), (5, 4000, 19500.0, 0, P_DEFAULT),
              (5, 4000, 38000.0, 0, P_DEFAULT), (2, 18000, 2500.0, 0, P_DEFAULT), (2, 18000, INF, 0, P_DEFAULT),
-             (5, 4000, 19500.0, F32, P_F32), (3, 32767, 3000.0, F32, P_F32)]
+             (5, 4000, 19500.0, F32, P_F32), (3, 32767, 3000.0, F32, P_F32), (3, 32767, INF, F32, P_F32)]
 
 
 @pytest.mark.parametrize("H,W,R,flags,prec", LONG_ROWS)
